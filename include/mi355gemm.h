@@ -1,0 +1,209 @@
+/*
+ * mi355gemm -- dense matrix product C = A * B on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the standard ("Cauchy") product of the paper's
+ * Implementation section (the equation for c_ij):
+ *
+ *     c_ij = sum_{r=0}^{k-1} a_ir * b_rj,     0 <= i < m, 0 <= j < n,
+ *
+ * for a row-major m x k matrix A and a row-major k x n matrix B.  The paper's
+ * (n x m) * (m x p) maps onto (m x k) * (k x n) here.  C is overwritten (no
+ * alpha/beta), as the paper's loops zero each c_ij before accumulating.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All functions are extern "C", never throw, and return an int status
+ *    (gemm_status_t).  On failure gemm_last_error() describes the cause.
+ *  - Matrix pointers are DEVICE pointers on the current HIP device, owned by
+ *    the caller, row-major, with row strides (lda, ldb, ldc) in ELEMENTS.
+ *    The caller keeps them alive until the enqueued work has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously; nothing synchronises the host unless
+ *    stated.
+ *  - Argument validation happens before any HIP call and touches no memory:
+ *    m, n, k >= 0; lda >= max(1,k); ldb >= max(1,n); ldc >= max(1,n);
+ *    non-NULL pointers for non-empty operands; a known mode; FP8 scales
+ *    finite and > 0; C must not overlap A or B.  Violations return
+ *    GEMM_EINVAL (or GEMM_EUNSUPPORTED for a mode an entry point lacks).
+ *  - k == 0 writes zeros to C (the empty sum); m == 0 or n == 0 is a no-op.
+ *  - A failing HIP call returns GEMM_EHIP with the HIP error text.
+ *  - Loading the library makes no HIP call; functions may be called from
+ *    several host threads (the tuning table is lock-protected).
+ */
+#ifndef MI355GEMM_H
+#define MI355GEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GEMM_OK = 0,
+    GEMM_PENDING = 1,        /* informational: serving request not done yet */
+    GEMM_EINVAL = -1,        /* bad argument */
+    GEMM_EUNSUPPORTED = -2,  /* valid but not supported by this entry point */
+    GEMM_ENOMEM = -3,        /* allocation failed or over the serving budget */
+    GEMM_EHIP = -4,          /* a HIP runtime call failed */
+    GEMM_EBUSY = -5,         /* serving queue full: retry later */
+    GEMM_ENOTFOUND = -6,     /* unknown ticket / file */
+    GEMM_EINTERNAL = -7
+} gemm_status_t;
+
+/* Arithmetic form of one product.  All forms accumulate in float32 and write
+ * float32 C.  Element type of A and B:
+ *   F32              float32  -- the paper's float product, on FP32 MFMA
+ *   BF16, F16        bfloat16 / binary16 codes (uint16)
+ *   F8E4M3           OCP FP8 E4M3 codes (uint8); C = scale_a*scale_b*(qA qB)
+ *   F32_SPLIT_BF16X3 float32; each operand is split in-kernel into
+ *                    hi = RNE_bf16(x), lo = RNE_bf16(x - hi) and
+ *                    C = hiA hiB + hiA loB + loA hiB (compensated BF16).   */
+typedef enum {
+    GEMM_MODE_F32 = 0,
+    GEMM_MODE_BF16 = 1,
+    GEMM_MODE_F16 = 2,
+    GEMM_MODE_F8E4M3 = 3,
+    GEMM_MODE_F32_SPLIT_BF16X3 = 4
+} gemm_mode_t;
+
+#define GEMM_NUM_MODES 5
+
+/* One product problem (row-major; C = A*B, C overwritten). */
+typedef struct gemm_problem {
+    int32_t mode;          /* gemm_mode_t */
+    int32_t flags;         /* reserved, must be 0 */
+    int64_t m, n, k;
+    const void *A;         /* m x k, element type by mode */
+    int64_t lda;
+    const void *B;         /* k x n, same element type as A */
+    int64_t ldb;
+    float *C;              /* m x n float32 */
+    int64_t ldc;
+    float scale_a;         /* F8E4M3 only: dequantisation factors, C = */
+    float scale_b;         /* scale_a*scale_b*sum(qa*qb); ignored otherwise */
+} gemm_problem_t;
+
+/* ---------------------------------------------------------------------- */
+/* Plain product (method steps: tile decomposition, LDS staging, MFMA      */
+/* inner product, split-K partial reduction, epilogue).                    */
+
+/* C = A*B for one problem, enqueued on `stream`.  The tile configuration
+ * and split-K factor come from the tuning table (shape-keyed); split-K
+ * partial sums go to a library-owned workspace and are summed in a fixed
+ * order, so a given (mode, m, n, k) always produces the same bits. */
+int gemm_plain(const gemm_problem_t *p, void *stream);
+
+/* As gemm_plain with an explicit tile configuration (index into
+ * gemm_config_info) and split-K factor (>= 1).  For tuning and tests. */
+int gemm_plain_cfg(const gemm_problem_t *p, int32_t cfg, int32_t split_k, void *stream);
+
+/* Number of tile configurations compiled for `mode`, and their geometry:
+ * info[0..5] = {BM, BN, BK, waves, lds_bytes, mfma_k}. */
+int gemm_num_configs(int32_t mode);
+int gemm_config_info(int32_t mode, int32_t cfg, int32_t info[6]);
+
+/* ---------------------------------------------------------------------- */
+/* Operand preparation (the reduced-precision forms' input conversion).    */
+
+/* out[i] = RNE(x[i]) in bfloat16 (to_mode = BF16) or binary16 (F16);
+ * `out` holds `count` uint16 codes.  Device pointers. */
+int gemm_convert_f32(const float *x, int64_t count, int32_t to_mode, void *out, void *stream);
+
+/* Per-tensor E4M3 quantisation: amax = max|x| (exact), s = amax/448 in
+ * float32 (1 for an all-zero tensor), q[i] = E4M3(RNE_sat(x[i]/s)) with the
+ * quotient rounded to float32.  `scale_out` is one float of DEVICE memory;
+ * `q` holds `count` uint8 codes. */
+int gemm_quantize_e4m3(const float *x, int64_t count, uint8_t *q, float *scale_out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Comparison reduction (normwise error against a binary64 reference).    */
+
+/* out3 (DEVICE, 3 doubles) = { sum (C-R)^2, sum R^2, max |C-R| } over the
+ * m x n matrices C (float32, ldc) and R (binary64, ldr), in binary64.
+ * The relative error is sqrt(out3[0] / out3[1]). */
+int gemm_errnorm(const float *C, int64_t ldc, const double *R, int64_t ldr,
+                 int64_t m, int64_t n, double *out3, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Grouped product: many independent problems in one persistent launch.   */
+
+/* All problems must share one mode (F32 or BF16/F16/F8E4M3/split).  The
+ * problem list is copied; device descriptors live in a library workspace
+ * reused by later calls on the same stream ordering (do not run two
+ * gemm_grouped calls concurrently on different streams). */
+int gemm_grouped(const gemm_problem_t *ps, int32_t count, void *stream);
+
+/* Build a graph that replays the grouped launch for this problem list
+ * (descriptors are uploaded once, into graph-owned device memory).  The
+ * problems' pointers must stay valid for the graph's lifetime. */
+int gemm_grouped_graph_create(const gemm_problem_t *ps, int32_t count, void **graph_out);
+int gemm_graph_launch(void *graph, void *stream);
+int gemm_graph_destroy(void *graph);
+
+/* ---------------------------------------------------------------------- */
+/* Tuning table (project autotuner).                                       */
+
+/* Time every legal configuration and split-K factor for this shape on the
+ * current device and record the fastest in the table (synchronises). */
+int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
+/* The (cfg, split_k) gemm_plain would use for this shape. */
+int gemm_tuner_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t *cfg, int32_t *split_k);
+int gemm_tuner_load(const char *path);
+int gemm_tuner_save(const char *path);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of arriving products.                      */
+
+typedef struct gemm_serve_config {
+    uint64_t hbm_budget_bytes;  /* admission limit on the sum of in-flight footprints */
+    int32_t max_inflight;       /* maximum admitted, unfinished requests */
+    int32_t num_streams;        /* device streams batches are spread over */
+    int32_t max_batch;          /* maximum requests in one launch */
+    int32_t queue_capacity;     /* maximum queued (not yet admitted) requests */
+    int32_t executor;           /* 0 = GPU, 1 = host fake executor (tests) */
+    int32_t fake_fail_every;    /* fake executor: fail every Nth batch (0 = never) */
+} gemm_serve_config_t;
+
+typedef struct gemm_serve_result {
+    int32_t status;             /* GEMM_OK when done, < 0 on failure */
+    int32_t batch_size;         /* requests in the launch that ran it */
+    uint64_t t_arrival_ns, t_admit_ns, t_launch_ns, t_done_ns;  /* steady clock */
+} gemm_serve_result_t;
+
+typedef struct gemm_serve_stats {
+    uint64_t submitted, completed, failed, batches;
+    uint64_t inflight_bytes, peak_inflight_bytes;
+    int32_t queued, inflight;
+} gemm_serve_stats_t;
+
+/* footprint = bytes(A) + bytes(B) + 4*m*n + split-K workspace. */
+int gemm_serve_footprint(const gemm_problem_t *p, uint64_t *bytes_out);
+int gemm_serve_create(const gemm_serve_config_t *cfg, void **server_out);
+/* Enqueue one request (copied); returns a monotonic ticket.  GEMM_ENOMEM if
+ * its footprint exceeds the budget, GEMM_EBUSY if the queue is full.
+ * t_arrival_ns = 0 stamps the current steady-clock time. */
+int gemm_serve_submit(void *server, const gemm_problem_t *p, uint64_t t_arrival_ns, uint64_t *ticket_out);
+/* GEMM_OK (done, result filled), GEMM_PENDING, or < 0. */
+int gemm_serve_poll(void *server, uint64_t ticket, gemm_serve_result_t *out);
+/* Block until every submitted request has finished. */
+int gemm_serve_drain(void *server);
+int gemm_serve_stats(void *server, gemm_serve_stats_t *out);
+/* Drains, then frees the server. */
+int gemm_serve_destroy(void *server);
+/* Current steady-clock time in ns (the clock of the serving timestamps). */
+uint64_t gemm_now_ns(void);
+
+/* ---------------------------------------------------------------------- */
+/* Diagnostics.                                                            */
+
+/* Thread-local text of the last failure (static storage; valid until the
+ * calling thread's next library call). */
+const char *gemm_last_error(void);
+int gemm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI355GEMM_H */

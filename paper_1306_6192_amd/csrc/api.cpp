@@ -1,0 +1,336 @@
+// C-ABI of the plain product, operand preparation, comparison reduction and
+// diagnostics.  Argument validation happens here, before any HIP call.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "host.hpp"
+
+namespace mg {
+
+static thread_local char t_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_err, sizeof(t_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { t_err[0] = 0; }
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+size_t elem_size(int mode) {
+    switch (mode) {
+        case GEMM_MODE_F32:
+        case GEMM_MODE_F32_SPLIT_BF16X3: return 4;
+        case GEMM_MODE_BF16:
+        case GEMM_MODE_F16: return 2;
+        case GEMM_MODE_F8E4M3: return 1;
+        default: return 0;
+    }
+}
+
+bool mode_known(int mode) { return mode >= 0 && mode < GEMM_NUM_MODES; }
+
+// Largest dimension the kernels index with 32-bit tile arithmetic.
+static const int64_t kMaxDim = (int64_t)1 << 30;
+
+static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+int validate(const gemm_problem_t *p) {
+    if (!p) return fail(GEMM_EINVAL, "problem pointer is NULL");
+    if (!mode_known(p->mode)) return fail(GEMM_EINVAL, "unknown mode %d", p->mode);
+    if (p->flags != 0) return fail(GEMM_EINVAL, "flags must be 0 (got %d)", p->flags);
+    if (p->m < 0 || p->n < 0 || p->k < 0)
+        return fail(GEMM_EINVAL, "negative dimension (m=%lld n=%lld k=%lld)", (long long)p->m,
+                    (long long)p->n, (long long)p->k);
+    if (p->m > kMaxDim || p->n > kMaxDim || p->k > kMaxDim)
+        return fail(GEMM_EUNSUPPORTED, "dimension above 2^30");
+    if (p->lda < std::max<int64_t>(1, p->k))
+        return fail(GEMM_EINVAL, "lda=%lld < max(1,k=%lld)", (long long)p->lda, (long long)p->k);
+    if (p->ldb < std::max<int64_t>(1, p->n))
+        return fail(GEMM_EINVAL, "ldb=%lld < max(1,n=%lld)", (long long)p->ldb, (long long)p->n);
+    if (p->ldc < std::max<int64_t>(1, p->n))
+        return fail(GEMM_EINVAL, "ldc=%lld < max(1,n=%lld)", (long long)p->ldc, (long long)p->n);
+    const bool out_empty = p->m == 0 || p->n == 0;
+    if (!out_empty && !p->C) return fail(GEMM_EINVAL, "C is NULL for a non-empty output");
+    if (!out_empty && p->k > 0 && (!p->A || !p->B))
+        return fail(GEMM_EINVAL, "A or B is NULL for a non-empty product");
+    if (p->mode == GEMM_MODE_F8E4M3) {
+        if (!(std::isfinite(p->scale_a) && p->scale_a > 0.f && std::isfinite(p->scale_b) &&
+              p->scale_b > 0.f))
+            return fail(GEMM_EINVAL, "FP8 scales must be finite and > 0");
+    }
+    if (!out_empty && p->k > 0) {
+        const size_t es = elem_size(p->mode);
+        const size_t cbytes = ((size_t)(p->m - 1) * p->ldc + p->n) * 4;
+        const size_t abytes = ((size_t)(p->m - 1) * p->lda + p->k) * es;
+        const size_t bbytes = ((size_t)(p->k - 1) * p->ldb + p->n) * es;
+        if (overlaps(p->C, cbytes, p->A, abytes) || overlaps(p->C, cbytes, p->B, bbytes))
+            return fail(GEMM_EINVAL, "C overlaps A or B");
+    }
+    return GEMM_OK;
+}
+
+int num_cus() {
+    static int cached = -1;
+    if (cached > 0) return cached;
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+        cached = n;
+    else
+        return 256;
+    return cached;
+}
+
+const KernelCfg *configs(int mode, int *count) {
+    if (mode == GEMM_MODE_F32) return f32_configs(count);
+    return lp_configs(mode, count);
+}
+
+static bool vec_ok(const void *ptr, int64_t ld, size_t es) {
+    return ((uintptr_t)ptr % 16 == 0) && ((ld * (int64_t)es) % 16 == 0);
+}
+
+Launch make_launch(const gemm_problem_t &p, const KernelCfg &kc, int split) {
+    Launch L;
+    TileProblem &P = L.P;
+    memset(&P, 0, sizeof(P));
+    const size_t es = elem_size(p.mode);
+    P.A = p.A;
+    P.B = p.B;
+    P.C = p.C;
+    P.lda = p.lda;
+    P.ldb = p.ldb;
+    P.ldc = p.ldc;
+    P.m = (int32_t)p.m;
+    P.n = (int32_t)p.n;
+    P.k = (int32_t)p.k;
+    P.tiles_m = (int32_t)((p.m + kc.bm - 1) / kc.bm);
+    P.tiles_n = (int32_t)((p.n + kc.bn - 1) / kc.bn);
+    const int nkt = (int)((p.k + kc.bk - 1) / kc.bk);
+    split = std::max(1, std::min(split, std::max(1, nkt)));
+    int per = (nkt + split - 1) / split;
+    if (per < 1) per = 1;
+    split = std::max(1, (nkt + per - 1) / per);
+    P.splits = split;
+    P.kt_per_split = per;
+    P.vec = (vec_ok(p.A, p.lda, es) ? 1 : 0) | (vec_ok(p.B, p.ldb, es) ? 2 : 0) |
+            (vec_ok(p.C, p.ldc, 4) ? 4 : 0);
+    P.scale = p.mode == GEMM_MODE_F8E4M3 ? p.scale_a * p.scale_b : 1.f;
+    P.split_stride = ((int64_t)p.m * p.n + 3) / 4 * 4;
+    L.splits = split;
+    L.nwg = P.tiles_m * P.tiles_n * split;
+    L.ws_bytes = split > 1 ? (int64_t)split * P.split_stride * 4 : 0;
+    return L;
+}
+
+int64_t plain_ws_bytes(const gemm_problem_t &p, int cfg, int split) {
+    int count = 0;
+    const KernelCfg *t = configs(p.mode, &count);
+    if (!t || cfg < 0 || cfg >= count || p.m == 0 || p.n == 0 || p.k == 0) return 0;
+    return make_launch(p, t[cfg], split).ws_bytes;
+}
+
+int enqueue_plain(const gemm_problem_t &p, int cfg, int split, void *ws, hipStream_t s) {
+    if (p.m == 0 || p.n == 0) return GEMM_OK;
+    if (p.k == 0) {
+        MG_HIP(launch_fill_zero(p.C, p.ldc, (int)p.m, (int)p.n, s));
+        return GEMM_OK;
+    }
+    int count = 0;
+    const KernelCfg *t = configs(p.mode, &count);
+    if (!t || count == 0) return fail(GEMM_EUNSUPPORTED, "mode %d has no kernels", p.mode);
+    if (cfg < 0 || cfg >= count) return fail(GEMM_EINVAL, "config %d out of range [0,%d)", cfg, count);
+    Launch L = make_launch(p, t[cfg], split);
+    if (L.splits > 1) {
+        if (!ws) return fail(GEMM_EINTERNAL, "split-K workspace missing");
+        L.P.C = static_cast<float *>(ws);
+    }
+    MG_HIP(t[cfg].plain(L.P, L.nwg, s));
+    if (L.splits > 1)
+        MG_HIP(launch_splitk_reduce(static_cast<const float *>(ws), L.P.split_stride, L.splits, L.P.scale,
+                                    p.C, p.ldc, (int)p.m, (int)p.n, s));
+    return GEMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device buffers.
+
+int DevBuf::ensure(size_t need, hipStream_t s) {
+    if (need <= bytes) return GEMM_OK;
+    if (ptr) {
+        MG_HIP(hipStreamSynchronize(s));
+        MG_HIP(hipFree(ptr));
+        ptr = nullptr;
+        bytes = 0;
+    }
+    size_t sz = std::max<size_t>(need, 1 << 20);
+    sz = (sz + 255) / 256 * 256;
+    if (hipMalloc(&ptr, sz) != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(GEMM_ENOMEM, "workspace allocation of %zu bytes failed", sz);
+    }
+    bytes = sz;
+    return GEMM_OK;
+}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+struct StreamWs {
+    DevBuf slot[4];
+};
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, StreamWs *> g_ws;
+
+DevBuf *stream_workspace(hipStream_t s, int slot) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    StreamWs *&w = g_ws[{dev, s}];
+    if (!w) w = new StreamWs();
+    return &w->slot[slot];
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+const char *gemm_last_error(void) { return t_err; }
+
+int gemm_version(void) { return 1; }
+
+uint64_t gemm_now_ns(void) { return now_ns(); }
+
+int gemm_num_configs(int32_t mode) {
+    clear_error();
+    if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
+    int count = 0;
+    configs(mode, &count);
+    return count;
+}
+
+int gemm_config_info(int32_t mode, int32_t cfg, int32_t info[6]) {
+    clear_error();
+    if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
+    if (!info) return fail(GEMM_EINVAL, "info is NULL");
+    int count = 0;
+    const KernelCfg *t = configs(mode, &count);
+    if (cfg < 0 || cfg >= count) return fail(GEMM_EINVAL, "config %d out of range", cfg);
+    info[0] = t[cfg].bm;
+    info[1] = t[cfg].bn;
+    info[2] = t[cfg].bk;
+    info[3] = t[cfg].waves;
+    info[4] = t[cfg].lds_bytes;
+    info[5] = t[cfg].mfma_k;
+    return GEMM_OK;
+}
+
+static int plain_common(const gemm_problem_t *p, int cfg, int split, void *stream) {
+    int rc = validate(p);
+    if (rc != GEMM_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->m == 0 || p->n == 0) return GEMM_OK;
+    void *ws = nullptr;
+    if (p->k > 0) {
+        int count = 0;
+        configs(p->mode, &count);
+        if (count == 0) return fail(GEMM_EUNSUPPORTED, "mode %d has no kernels", p->mode);
+        const int64_t need = plain_ws_bytes(*p, cfg, split);
+        if (need > 0) {
+            DevBuf *b = stream_workspace(s, 0);
+            rc = b->ensure((size_t)need, s);
+            if (rc != GEMM_OK) return rc;
+            ws = b->ptr;
+        }
+    }
+    return enqueue_plain(*p, cfg, split, ws, s);
+}
+
+int gemm_plain(const gemm_problem_t *p, void *stream) {
+    clear_error();
+    int rc = validate(p);
+    if (rc != GEMM_OK) return rc;
+    int cfg = 0, split = 1;
+    tuner_choose(p->mode, p->m, p->n, p->k, &cfg, &split);
+    return plain_common(p, cfg, split, stream);
+}
+
+int gemm_plain_cfg(const gemm_problem_t *p, int32_t cfg, int32_t split_k, void *stream) {
+    clear_error();
+    if (split_k < 1) return fail(GEMM_EINVAL, "split_k must be >= 1");
+    int rc = validate(p);
+    if (rc != GEMM_OK) return rc;
+    int count = 0;
+    configs(p->mode, &count);
+    if (count == 0) return fail(GEMM_EUNSUPPORTED, "mode %d has no kernels", p->mode);
+    if (cfg < 0 || cfg >= count) return fail(GEMM_EINVAL, "config %d out of range [0,%d)", cfg, count);
+    return plain_common(p, cfg, split_k, stream);
+}
+
+int gemm_convert_f32(const float *x, int64_t count, int32_t to_mode, void *out, void *stream) {
+    clear_error();
+    if (count < 0) return fail(GEMM_EINVAL, "negative count");
+    if (to_mode != GEMM_MODE_BF16 && to_mode != GEMM_MODE_F16)
+        return fail(GEMM_EINVAL, "to_mode must be BF16 or F16");
+    if (count == 0) return GEMM_OK;
+    if (!x || !out) return fail(GEMM_EINVAL, "NULL buffer");
+    if (overlaps(x, (size_t)count * 4, out, (size_t)count * 2)) return fail(GEMM_EINVAL, "buffers overlap");
+    MG_HIP(launch_convert_f32(x, count, to_mode, out, (hipStream_t)stream));
+    return GEMM_OK;
+}
+
+int gemm_quantize_e4m3(const float *x, int64_t count, uint8_t *q, float *scale_out, void *stream) {
+    clear_error();
+    if (count < 0) return fail(GEMM_EINVAL, "negative count");
+    if (!scale_out) return fail(GEMM_EINVAL, "scale_out is NULL");
+    if (count > 0 && (!x || !q)) return fail(GEMM_EINVAL, "NULL buffer");
+    if (count > 0 && overlaps(x, (size_t)count * 4, q, (size_t)count)) return fail(GEMM_EINVAL, "buffers overlap");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf *b = stream_workspace(s, 2);
+    int rc = b->ensure(4096, s);
+    if (rc != GEMM_OK) return rc;
+    MG_HIP(launch_quantize_e4m3(x, count, q, scale_out, static_cast<uint32_t *>(b->ptr), s));
+    return GEMM_OK;
+}
+
+int gemm_errnorm(const float *C, int64_t ldc, const double *R, int64_t ldr, int64_t m, int64_t n,
+                 double *out3, void *stream) {
+    clear_error();
+    if (m < 0 || n < 0) return fail(GEMM_EINVAL, "negative dimension");
+    if (!out3) return fail(GEMM_EINVAL, "out3 is NULL");
+    if (ldc < std::max<int64_t>(1, n) || ldr < std::max<int64_t>(1, n)) return fail(GEMM_EINVAL, "bad ld");
+    if (m * n > 0 && (!C || !R)) return fail(GEMM_EINVAL, "NULL matrix");
+    hipStream_t s = (hipStream_t)stream;
+    const int nparts = 2048;
+    DevBuf *b = stream_workspace(s, 2);
+    int rc = b->ensure(4096 + (size_t)nparts * 3 * sizeof(double), s);
+    if (rc != GEMM_OK) return rc;
+    double *partials = reinterpret_cast<double *>(static_cast<char *>(b->ptr) + 4096);
+    MG_HIP(launch_errnorm(C, ldc, R, ldr, m, n, out3, partials, nparts, s));
+    return GEMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Host-side internals shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace mg {
+
+// Record a failure for gemm_last_error() and return `code`.
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define MG_HIP(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return ::mg::fail(GEMM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t elem_size(int mode);
+bool mode_known(int mode);
+
+// Synchronous argument checks; no HIP call, no memory access.
+int validate(const gemm_problem_t *p);
+
+// Number of compute units of the current device (256 if it cannot be read).
+int num_cus();
+
+// Kernel configuration table of a mode.
+const KernelCfg *configs(int mode, int *count);
+
+// The TileProblem of one problem for one configuration and split-K factor
+// (split is normalised so that no split is empty; C is left to the caller
+// when split > 1).
+struct Launch {
+    TileProblem P;
+    int nwg;
+    int splits;
+    int64_t ws_bytes;
+};
+Launch make_launch(const gemm_problem_t &p, const KernelCfg &kc, int split);
+
+// Enqueue one plain product with an explicit configuration.  `ws` must hold
+// `Launch::ws_bytes` when the split is above 1.
+int enqueue_plain(const gemm_problem_t &p, int cfg, int split, void *ws, hipStream_t s);
+
+// Split-K workspace bytes the (cfg, split) choice needs for this problem.
+int64_t plain_ws_bytes(const gemm_problem_t &p, int cfg, int split);
+
+// Tuning table.
+void tuner_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg, int *split);
+void heuristic_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg, int *split);
+
+// A device buffer owned by the library that grows on demand.  Growth waits
+// for `s` to drain before freeing the old allocation.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need, hipStream_t s);
+    void release();
+};
+
+// Per-stream library workspace (split-K slabs, grouped descriptors).
+DevBuf *stream_workspace(hipStream_t s, int slot);
+
+uint64_t now_ns();
+
+}  // namespace mg

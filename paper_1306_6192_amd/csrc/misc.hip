@@ -1,0 +1,220 @@
+// Elementwise and reduction kernels around the product: zero fill (k = 0),
+// split-K partial reduction, operand conversion for the reduced-precision
+// forms, and the binary64 comparison reduction.
+#include "kernels.hpp"
+
+// --------------------------------------------------------------------------
+// C = 0 (the empty sum, k == 0).
+__global__ void fill_zero_kernel(float *C, int64_t ldc, int m, int n) {
+    const int64_t total = (int64_t)m * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / n, c = i - r * n;
+        C[r * ldc + c] = 0.f;
+    }
+}
+
+static int grid_for(int64_t work, int per_block, int cap = 4096) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_fill_zero(float *C, int64_t ldc, int m, int n, hipStream_t s) {
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for((int64_t)m * n, 256)), dim3(256), 0, s, C, ldc,
+                       m, n);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Split-K: C[i][j] = scale * sum_{p=0}^{S-1} ws[p][i][j], summed in ascending
+// p so the result does not depend on which workgroup finished first.
+__global__ void splitk_reduce_kernel(const float *__restrict__ ws, int64_t split_stride, int splits,
+                                     float scale, float *__restrict__ C, int64_t ldc, int m, int n) {
+    const int64_t total = (int64_t)m * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float acc = ws[i];
+        for (int p = 1; p < splits; ++p) acc += ws[p * split_stride + i];
+        const int64_t r = i / n, c = i - r * n;
+        C[r * ldc + c] = acc * scale;
+    }
+}
+
+hipError_t launch_splitk_reduce(const float *ws, int64_t split_stride, int splits, float scale,
+                                float *C, int64_t ldc, int m, int n, hipStream_t s) {
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for((int64_t)m * n, 256, 8192)), dim3(256), 0, s,
+                       ws, split_stride, splits, scale, C, ldc, m, n);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// float32 -> bfloat16, round to nearest even: add half an ulp of the kept
+// part (0x7FFF) plus the kept part's lowest bit, then truncate.  NaN stays a
+// quiet NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+    const uint32_t u = __float_as_uint(x);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void convert_bf16_kernel(const float *__restrict__ x, int64_t count, uint16_t *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = f32_to_bf16_rne(x[i]);
+}
+
+__global__ void convert_f16_kernel(const float *__restrict__ x, int64_t count, _Float16 *__restrict__ out) {
+    // The hardware conversion rounds to nearest even (default mode).
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (_Float16)x[i];
+}
+
+hipError_t launch_convert_f32(const float *x, int64_t count, int to_mode, void *out, hipStream_t s) {
+    const int g = grid_for(count, 256, 16384);
+    if (to_mode == GEMM_MODE_BF16)
+        hipLaunchKernelGGL(convert_bf16_kernel, dim3(g), dim3(256), 0, s, x, count, (uint16_t *)out);
+    else
+        hipLaunchKernelGGL(convert_f16_kernel, dim3(g), dim3(256), 0, s, x, count, (_Float16 *)out);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// OCP E4M3 ("fn") encoding of a float32 value, round to nearest even with
+// saturation to +-448.  Normal codes: value = 2^(E-7) * (1 + F/8), E in
+// 1..15 (E = 15, F = 7 is NaN, so 448 = 2^8 * 1.75 is the largest);
+// subnormals: value = F * 2^-9.
+__device__ __forceinline__ uint8_t f32_to_e4m3_sat(float x) {
+    const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+    const float a = fabsf(x);
+    uint32_t code;
+    if (!(a < 448.f)) {
+        code = 0x7E;                                   // saturate (also NaN -> 448)
+    } else if (a < 0.015625f) {                        // below 2^-6: subnormal grid of 2^-9
+        code = (uint32_t)__builtin_rintf(a * 512.f);   // exact scaling, then RNE; 8 -> 0x08 = 2^-6
+    } else {
+        int e;
+        const float f = frexpf(a, &e);                 // a = f * 2^e, f in [0.5, 1)
+        const int E = e - 1;                           // a = (2f) * 2^E, 2f in [1, 2)
+        uint32_t F = (uint32_t)__builtin_rintf((2.f * f - 1.f) * 8.f);  // exact, then RNE
+        int Eb = E + 7;
+        if (F == 8) { F = 0; ++Eb; }
+        code = ((uint32_t)Eb << 3) | F;
+        if (code > 0x7E) code = 0x7E;
+    }
+    return (uint8_t)(sign | code);
+}
+
+__global__ void zero_u32_kernel(uint32_t *p) { *p = 0u; }
+
+// amax via the bit patterns of |x|: for non-negative floats the unsigned
+// order of the bits is the numeric order, so an integer max is exact.
+__global__ void amax_kernel(const float *__restrict__ x, int64_t count, uint32_t *amax_bits) {
+    uint32_t m = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, __float_as_uint(x[i]) & 0x7FFFFFFFu);
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    __shared__ uint32_t wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = wmax[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = max(b, wmax[w]);
+        atomicMax(amax_bits, b);
+    }
+}
+
+__global__ void quantize_e4m3_kernel(const float *__restrict__ x, int64_t count, uint8_t *__restrict__ q,
+                                     const uint32_t *amax_bits, float *scale_out) {
+    const float amax = __uint_as_float(*amax_bits);
+    const float s = (amax == 0.f) ? 1.f : amax / 448.f;   // IEEE division
+    if (blockIdx.x == 0 && threadIdx.x == 0) *scale_out = s;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        q[i] = f32_to_e4m3_sat(x[i] / s);
+}
+
+hipError_t launch_quantize_e4m3(const float *x, int64_t count, uint8_t *q, float *scale_out,
+                                uint32_t *amax_scratch, hipStream_t s) {
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, amax_scratch);
+    const int g = grid_for(count, 256, 4096);
+    hipLaunchKernelGGL(amax_kernel, dim3(g), dim3(256), 0, s, x, count, amax_scratch);
+    hipLaunchKernelGGL(quantize_e4m3_kernel, dim3(grid_for(count, 256, 16384)), dim3(256), 0, s, x, count, q,
+                       amax_scratch, scale_out);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Comparison reduction in binary64: per-block partial (sum d^2, sum R^2,
+// max |d|) over a grid-stride walk, then one block folds the partials in
+// index order, so the result is independent of scheduling.
+__device__ __forceinline__ void reduce3_block(double &a, double &b, double &c, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        c = fmax(c, __shfl_xor(c, off));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[3 * w] = a;
+        sh[3 * w + 1] = b;
+        sh[3 * w + 2] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            a += sh[3 * i];
+            b += sh[3 * i + 1];
+            c = fmax(c, sh[3 * i + 2]);
+        }
+    }
+}
+
+__global__ void errnorm_partial_kernel(const float *__restrict__ C, int64_t ldc, const double *__restrict__ R,
+                                       int64_t ldr, int64_t m, int64_t n, double *partials) {
+    double sd = 0.0, sr = 0.0, mx = 0.0;
+    const int64_t total = m * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / n, c = i - r * n;
+        const double ref = R[r * ldr + c];
+        const double d = (double)C[r * ldc + c] - ref;
+        sd = fma(d, d, sd);
+        sr = fma(ref, ref, sr);
+        mx = fmax(mx, fabs(d));
+    }
+    __shared__ double sh[3 * 4];
+    reduce3_block(sd, sr, mx, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = sd;
+        partials[3 * blockIdx.x + 1] = sr;
+        partials[3 * blockIdx.x + 2] = mx;
+    }
+}
+
+__global__ void errnorm_final_kernel(const double *partials, int nparts, double *out3) {
+    double sd = 0.0, sr = 0.0, mx = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        sd += partials[3 * i];
+        sr += partials[3 * i + 1];
+        mx = fmax(mx, partials[3 * i + 2]);
+    }
+    __shared__ double sh[3 * 4];
+    reduce3_block(sd, sr, mx, sh);
+    if (threadIdx.x == 0) {
+        out3[0] = sd;
+        out3[1] = sr;
+        out3[2] = mx;
+    }
+}
+
+hipError_t launch_errnorm(const float *C, int64_t ldc, const double *R, int64_t ldr, int64_t m, int64_t n,
+                          double *out3, double *partials, int nparts, hipStream_t s) {
+    const int g = grid_for(m * n, 256, nparts);
+    hipLaunchKernelGGL(errnorm_partial_kernel, dim3(g), dim3(256), 0, s, C, ldc, R, ldr, m, n, partials);
+    hipLaunchKernelGGL(errnorm_final_kernel, dim3(1), dim3(256), 0, s, partials, g, out3);
+    return hipGetLastError();
+}

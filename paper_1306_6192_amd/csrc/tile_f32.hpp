@@ -1,0 +1,241 @@
+// FP32 output tile of C = A*B on gfx950 matrix cores (v_mfma_f32_32x32x2_f32).
+//
+// One 256-lane workgroup (4 waves, 2 x 2) owns a BM x BN tile of C and walks
+// the k dimension in k-tiles of BK = 32:
+//   HBM/L2 -> registers (16-B loads, masked at the edges)
+//          -> LDS (two stages, rows padded against bank conflicts)
+//          -> MFMA fragments -> float32 accumulators in AGPRs/VGPRs.
+// The next k-tile's global loads are issued before the current k-tile's
+// MFMAs, and written to the other LDS stage after them: one barrier per
+// k-tile.  This is the shared-memory tiling of the paper's Listing 4
+// (Implementation section: stage A and B sub-matrices in on-chip memory,
+// synchronise, multiply from on-chip memory, synchronise) re-shaped for
+// 64-wide waves and matrix-core instructions.
+//
+// MFMA operand layout (32x32x2, f32): lane l supplies A[l%32][kslot(l/32)]
+// and B[kslot(l/32)][l%32]; the 32x32 result has, in lane l and register r,
+// row 8*(r/4) + 4*(l/32) + r%4 and column l%32.
+//
+// k order: within a chunk of 8 consecutive k, MFMA step t (0..3) consumes
+// k = 8c + t in lanes 0..31 and k = 8c + 4 + t in lanes 32..63, so that each
+// lane reads its four A values with one 16-B LDS read.  Every configuration
+// of this file visits the chunks in the same order, so the summation order of
+// an output element does not depend on BM/BN (only split-K changes it).
+//
+// Columns: lane l%32 = jj of a wave owning TN = 32*CB columns reads the CB
+// consecutive B values at column CB*jj (one LDS read of CB floats) and feeds
+// value cb to the accumulator block cb; block cb, lane column jj is therefore
+// output column CB*jj + cb, and the epilogue stores CB consecutive floats.
+#pragma once
+
+#include "common.hpp"
+
+template <int BM_, int BN_>
+struct F32Cfg {
+    static constexpr int BM = BM_, BN = BN_, BK = 32;
+    static constexpr int WM = 2, WN = 2;              // waves along m and n
+    static constexpr int TM = BM / WM, TN = BN / WN;  // wave tile
+    static constexpr int RB = TM / 32, CB = TN / 32;  // 32x32 blocks per wave
+    static constexpr int SA = BK + 4;                 // LDS row stride of A (floats)
+    static constexpr int SB = BN + 4;                 // LDS row stride of B (floats)
+    static constexpr int A_ELEMS = BM * SA, B_ELEMS = BK * SB;
+    static constexpr int STAGE = A_ELEMS + B_ELEMS;
+    static constexpr int LDS_FLOATS = 2 * STAGE;
+    static constexpr int LDS_BYTES = LDS_FLOATS * 4;
+    static constexpr int AV = BM * BK / 4 / GEMM_THREADS;  // float4 loads per thread (A)
+    static constexpr int BV = BK * BN / 4 / GEMM_THREADS;  // float4 loads per thread (B)
+    static_assert(RB >= 1 && (CB == 1 || CB == 2 || CB == 4), "wave tile");
+    static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+};
+
+template <int CB> struct FVec;
+template <> struct FVec<1> { typedef float T; };
+template <> struct FVec<2> { typedef f32x2 T; };
+template <> struct FVec<4> { typedef f32x4 T; };
+
+// Four consecutive floats of row r starting at column c, zero outside
+// [0,R) x [0,Cn).  `vec` promises 16-B alignment of every row start.
+__device__ __forceinline__ f32x4 f32_load4(const float *__restrict__ P, int64_t ld, int r, int c,
+                                           int R, int Cn, bool vec) {
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (r < R) {
+        const float *p = P + (int64_t)r * ld + c;
+        if (vec && c + 3 < Cn) {
+            v = *reinterpret_cast<const f32x4 *>(p);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (c + e < Cn) v[e] = p[e];
+        }
+    }
+    return v;
+}
+
+template <class Cfg>
+__device__ __forceinline__ void f32_load_tiles(const TileProblem &P, int m0, int n0, int k0,
+                                               f32x4 (&ra)[Cfg::AV], f32x4 (&rb)[Cfg::BV]) {
+    const int tid = threadIdx.x;
+    const float *A = static_cast<const float *>(P.A);
+    const float *B = static_cast<const float *>(P.B);
+#pragma unroll
+    for (int q = 0; q < Cfg::AV; ++q) {
+        const int idx = tid + q * GEMM_THREADS;
+        const int r = idx / (Cfg::BK / 4);
+        const int kv = (idx % (Cfg::BK / 4)) * 4;
+        ra[q] = f32_load4(A, P.lda, m0 + r, k0 + kv, P.m, P.k, P.vec & 1);
+    }
+#pragma unroll
+    for (int q = 0; q < Cfg::BV; ++q) {
+        const int idx = tid + q * GEMM_THREADS;
+        const int kr = idx / (Cfg::BN / 4);
+        const int cv = (idx % (Cfg::BN / 4)) * 4;
+        rb[q] = f32_load4(B, P.ldb, k0 + kr, n0 + cv, P.k, P.n, P.vec & 2);
+    }
+}
+
+template <class Cfg>
+__device__ __forceinline__ void f32_store_tiles(float *stage, const f32x4 (&ra)[Cfg::AV],
+                                                const f32x4 (&rb)[Cfg::BV]) {
+    const int tid = threadIdx.x;
+    float *As = stage;
+    float *Bs = stage + Cfg::A_ELEMS;
+#pragma unroll
+    for (int q = 0; q < Cfg::AV; ++q) {
+        const int idx = tid + q * GEMM_THREADS;
+        const int r = idx / (Cfg::BK / 4);
+        const int kv = (idx % (Cfg::BK / 4)) * 4;
+        *reinterpret_cast<f32x4 *>(&As[r * Cfg::SA + kv]) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < Cfg::BV; ++q) {
+        const int idx = tid + q * GEMM_THREADS;
+        const int kr = idx / (Cfg::BN / 4);
+        const int cv = (idx % (Cfg::BN / 4)) * 4;
+        *reinterpret_cast<f32x4 *>(&Bs[kr * Cfg::SB + cv]) = rb[q];
+    }
+}
+
+template <class Cfg>
+__device__ __forceinline__ void f32_compute_stage(const float *stage, f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+    typedef typename FVec<Cfg::CB>::T BVec;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
+    const int l32 = lane & 31, g = lane >> 5;
+    const float *As = stage + (wm * Cfg::TM + l32) * Cfg::SA + 4 * g;
+    const float *Bs = stage + Cfg::A_ELEMS + (4 * g) * Cfg::SB + wn * Cfg::TN + Cfg::CB * l32;
+#pragma unroll
+    for (int kc = 0; kc < Cfg::BK / 8; ++kc) {
+        f32x4 af[Cfg::RB];
+        BVec bf[4];
+#pragma unroll
+        for (int rb = 0; rb < Cfg::RB; ++rb)
+            af[rb] = *reinterpret_cast<const f32x4 *>(As + rb * 32 * Cfg::SA + kc * 8);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            bf[t] = *reinterpret_cast<const BVec *>(Bs + (kc * 8 + t) * Cfg::SB);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int rb = 0; rb < Cfg::RB; ++rb) {
+#pragma unroll
+                for (int cb = 0; cb < Cfg::CB; ++cb) {
+                    float bv;
+                    if constexpr (Cfg::CB == 1) bv = bf[t];
+                    else bv = bf[t][cb];
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[rb][t], bv, acc[rb][cb], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
+// Store the accumulators of one tile to C (or to a split-K partial slab).
+// Lane l, block (rb, cb), register r holds row 8*(r/4) + 4*(l/32) + r%4 of
+// the block and output column CB*(l%32) + cb of the wave's columns.
+template <class Cfg>
+__device__ __forceinline__ void f32_epilogue(float *__restrict__ C, int64_t ldc, int M, int N,
+                                             int m0, int n0, bool vec, float scale,
+                                             const f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
+    const int l32 = lane & 31, g = lane >> 5;
+    const int col = n0 + wn * Cfg::TN + Cfg::CB * l32;
+    const bool full_cols = vec && (col + Cfg::CB <= N);
+#pragma unroll
+    for (int rb = 0; rb < Cfg::RB; ++rb) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = m0 + wm * Cfg::TM + rb * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+            if (row >= M) continue;
+            float *p = C + (int64_t)row * ldc + col;
+            if constexpr (Cfg::CB == 4) {
+                f32x4 v = {acc[rb][0][r] * scale, acc[rb][1][r] * scale, acc[rb][2][r] * scale,
+                           acc[rb][3][r] * scale};
+                if (full_cols) {
+                    *reinterpret_cast<f32x4 *>(p) = v;
+                    continue;
+                }
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    if (col + cb < N) p[cb] = v[cb];
+            } else if constexpr (Cfg::CB == 2) {
+                f32x2 v = {acc[rb][0][r] * scale, acc[rb][1][r] * scale};
+                if (full_cols) {
+                    *reinterpret_cast<f32x2 *>(p) = v;
+                    continue;
+                }
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    if (col + cb < N) p[cb] = v[cb];
+            } else {
+                if (col < N) p[0] = acc[rb][0][r] * scale;
+            }
+        }
+    }
+}
+
+// One BM x BN output tile over the k-tiles of split `split`.
+template <class Cfg>
+__device__ __forceinline__ void f32_tile(const TileProblem &P, int tm, int tn, int split, float *lds) {
+    const int m0 = tm * Cfg::BM, n0 = tn * Cfg::BN;
+    const int nkt = (P.k + Cfg::BK - 1) / Cfg::BK;
+    const int kt0 = split * P.kt_per_split;
+    const int kt1 = min(kt0 + P.kt_per_split, nkt);
+
+    f32x16 acc[Cfg::RB][Cfg::CB];
+#pragma unroll
+    for (int rb = 0; rb < Cfg::RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < Cfg::CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[rb][cb][r] = 0.f;
+
+    f32x4 ra[Cfg::AV], rbv[Cfg::BV];
+    if (kt0 < kt1) {
+        f32_load_tiles<Cfg>(P, m0, n0, kt0 * Cfg::BK, ra, rbv);
+        f32_store_tiles<Cfg>(lds, ra, rbv);
+    }
+    __syncthreads();
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const int cur = (kt - kt0) & 1;
+        const bool more = kt + 1 < kt1;
+        if (more) f32_load_tiles<Cfg>(P, m0, n0, (kt + 1) * Cfg::BK, ra, rbv);
+        f32_compute_stage<Cfg>(lds + cur * Cfg::STAGE, acc);
+        if (more) f32_store_tiles<Cfg>(lds + (cur ^ 1) * Cfg::STAGE, ra, rbv);
+        __syncthreads();
+    }
+
+    float *C = P.C;
+    int64_t ldc = P.ldc;
+    bool vec = (P.vec & 4) != 0;
+    if (P.splits > 1) {
+        C = P.C + (int64_t)split * P.split_stride;
+        ldc = P.n;
+        vec = (P.n % 4) == 0;
+    }
+    // Split-K partials are stored unscaled; the reduction applies the scale.
+    f32_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, vec, P.splits > 1 ? 1.f : P.scale, acc);
+}

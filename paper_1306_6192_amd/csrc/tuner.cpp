@@ -1,0 +1,242 @@
+// Tile-configuration autotuner: a shape-keyed table of (config, split-K)
+// choices, filled by measurement (gemm_tune) or by a cost model when a shape
+// has not been measured.  The choice depends on (mode, m, n, k) only, never
+// on load, so a shape gets the same configuration -- and therefore the same
+// summation order -- on every path.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "host.hpp"
+
+namespace mg {
+
+typedef std::tuple<int, int64_t, int64_t, int64_t> Key;
+
+static std::mutex g_mu;
+static std::map<Key, std::pair<int, int>> g_table;
+static bool g_env_loaded = false;
+
+static int load_file_locked(const char *path);
+
+// Relative sustained efficiency of a workgroup tile (larger tiles reuse each
+// staged operand more often and hide the per-k-tile barrier better).
+static double tile_eff(const KernelCfg &kc) {
+    const double area = (double)kc.bm * kc.bn;
+    if (area >= 65536) return 1.00;
+    if (area >= 32768) return 0.92;
+    if (area >= 16384) return 0.82;
+    if (area >= 8192) return 0.62;
+    return 0.45;
+}
+
+void heuristic_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg_out, int *split_out) {
+    int count = 0;
+    const KernelCfg *t = configs(mode, &count);
+    *cfg_out = 0;
+    *split_out = 1;
+    if (!t || count == 0 || m == 0 || n == 0 || k == 0) return;
+    const double cus = (double)num_cus();
+    double best = 1e300;
+    for (int c = 0; c < count; ++c) {
+        const KernelCfg &kc = t[c];
+        const int64_t tiles = ((m + kc.bm - 1) / kc.bm) * ((n + kc.bn - 1) / kc.bn);
+        const int64_t nkt = (k + kc.bk - 1) / kc.bk;
+        for (int split = 1; split <= 16; split *= 2) {
+            if (split > 1 && nkt / split < 4) break;
+            const int64_t per = (nkt + split - 1) / split;
+            const int64_t wgs = tiles * split;
+            const double slots = cus * std::max(1, kc.wg_per_cu);
+            const double rounds = std::ceil((double)wgs / slots);
+            // time ~ rounds * (work of one CU slot-set) / efficiency
+            const double per_round = (double)std::max(1, kc.wg_per_cu) * kc.bm * kc.bn * (double)(per * kc.bk);
+            double cost = rounds * per_round / tile_eff(kc);
+            // split-K pays for writing and re-reading the partial slabs
+            if (split > 1) cost += (double)(split + 1) * (double)m * n * 64.0 / cus;
+            // a launch that cannot reach every CU also leaves HBM bandwidth idle
+            if ((double)wgs < cus) cost *= 1.0 + 0.25 * (1.0 - (double)wgs / cus);
+            if (cost < best * 0.999) {
+                best = cost;
+                *cfg_out = c;
+                *split_out = split;
+            }
+        }
+    }
+}
+
+void tuner_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg, int *split) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_env_loaded) {
+            g_env_loaded = true;
+            const char *env = getenv("MI355GEMM_TUNE_FILE");
+            if (env && *env) (void)load_file_locked(env);
+        }
+        auto it = g_table.find(Key(mode, m, n, k));
+        if (it != g_table.end()) {
+            *cfg = it->second.first;
+            *split = it->second.second;
+            return;
+        }
+    }
+    heuristic_choose(mode, m, n, k, cfg, split);
+}
+
+static int load_file_locked(const char *path) {
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(GEMM_ENOTFOUND, "cannot open tuning file %s", path);
+    char line[512];
+    int n_ok = 0;
+    while (fgets(line, sizeof(line), f)) {
+        int mode, cfg, split;
+        long long m, n, k;
+        if (sscanf(line, " {\"mode\": %d, \"m\": %lld, \"n\": %lld, \"k\": %lld, \"cfg\": %d, \"split\": %d",
+                   &mode, &m, &n, &k, &cfg, &split) == 6) {
+            int count = 0;
+            configs(mode, &count);
+            if (mode_known(mode) && cfg >= 0 && cfg < count && split >= 1) {
+                g_table[Key(mode, m, n, k)] = {cfg, split};
+                ++n_ok;
+            }
+        }
+    }
+    fclose(f);
+    return n_ok;
+}
+
+// Time one (cfg, split) choice: median of `reps` event-timed launches.
+static int time_choice(const gemm_problem_t &p, int cfg, int split, void *ws, hipStream_t s, float *ms_out) {
+    hipEvent_t e0, e1;
+    MG_HIP(hipEventCreate(&e0));
+    MG_HIP(hipEventCreate(&e1));
+    const int reps = 5;
+    float ts[reps];
+    int rc = enqueue_plain(p, cfg, split, ws, s);  // warm-up
+    for (int r = 0; r < reps && rc == GEMM_OK; ++r) {
+        (void)hipEventRecord(e0, s);
+        rc = enqueue_plain(p, cfg, split, ws, s);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = fail(GEMM_EHIP, "event sync failed");
+        (void)hipEventElapsedTime(&ts[r], e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != GEMM_OK) return rc;
+    std::sort(ts, ts + reps);
+    *ms_out = ts[reps / 2];
+    return GEMM_OK;
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+int gemm_tuner_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t *cfg, int32_t *split_k) {
+    clear_error();
+    if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
+    if (!cfg || !split_k) return fail(GEMM_EINVAL, "NULL output");
+    if (m < 0 || n < 0 || k < 0) return fail(GEMM_EINVAL, "negative dimension");
+    int c = 0, s = 1;
+    tuner_choose(mode, m, n, k, &c, &s);
+    *cfg = c;
+    *split_k = s;
+    return GEMM_OK;
+}
+
+int gemm_tuner_load(const char *path) {
+    clear_error();
+    if (!path) return fail(GEMM_EINVAL, "path is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    const int rc = load_file_locked(path);
+    return rc < 0 ? rc : GEMM_OK;
+}
+
+int gemm_tuner_save(const char *path) {
+    clear_error();
+    if (!path) return fail(GEMM_EINVAL, "path is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(GEMM_ENOTFOUND, "cannot write %s", path);
+    for (auto &kv : g_table) {
+        fprintf(f, "{\"mode\": %d, \"m\": %lld, \"n\": %lld, \"k\": %lld, \"cfg\": %d, \"split\": %d}\n",
+                std::get<0>(kv.first), (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
+                (long long)std::get<3>(kv.first), kv.second.first, kv.second.second);
+    }
+    fclose(f);
+    return GEMM_OK;
+}
+
+int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream) {
+    clear_error();
+    if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
+    if (m <= 0 || n <= 0 || k <= 0) return fail(GEMM_EINVAL, "tuning needs a non-empty product");
+    int count = 0;
+    const KernelCfg *t = configs(mode, &count);
+    if (!t || count == 0) return fail(GEMM_EUNSUPPORTED, "mode %d has no kernels", mode);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t es = elem_size(mode);
+    void *A = nullptr, *B = nullptr, *C = nullptr, *ws = nullptr;
+    int64_t ws_need = 0;
+    gemm_problem_t p;
+    memset(&p, 0, sizeof(p));
+    p.mode = mode;
+    p.m = m;
+    p.n = n;
+    p.k = k;
+    p.lda = k;
+    p.ldb = n;
+    p.ldc = n;
+    p.scale_a = p.scale_b = 1.f;
+    for (int c = 0; c < count; ++c)
+        for (int sp = 1; sp <= 16; sp *= 2) ws_need = std::max(ws_need, plain_ws_bytes(p, c, sp));
+    int rc = GEMM_OK;
+    if (hipMalloc(&A, (size_t)m * k * es) != hipSuccess || hipMalloc(&B, (size_t)k * n * es) != hipSuccess ||
+        hipMalloc(&C, (size_t)m * n * 4) != hipSuccess ||
+        (ws_need > 0 && hipMalloc(&ws, (size_t)ws_need) != hipSuccess)) {
+        (void)hipGetLastError();
+        rc = fail(GEMM_ENOMEM, "tuning buffers do not fit");
+    }
+    int best_c = 0, best_s = 1;
+    float best_ms = 1e30f;
+    if (rc == GEMM_OK) {
+        (void)hipMemsetAsync(A, 0, (size_t)m * k * es, s);
+        (void)hipMemsetAsync(B, 0, (size_t)k * n * es, s);
+        p.A = A;
+        p.B = B;
+        p.C = static_cast<float *>(C);
+        for (int c = 0; c < count && rc == GEMM_OK; ++c) {
+            const int64_t nkt = (k + t[c].bk - 1) / t[c].bk;
+            int last_split = 0;
+            for (int sp = 1; sp <= 16 && rc == GEMM_OK; sp *= 2) {
+                if (sp > 1 && nkt / sp < 4) break;
+                const int eff = make_launch(p, t[c], sp).splits;
+                if (eff == last_split) continue;
+                last_split = eff;
+                float ms = 0.f;
+                rc = time_choice(p, c, sp, ws, s, &ms);
+                if (rc == GEMM_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best_c = c;
+                    best_s = eff;
+                }
+            }
+        }
+    }
+    if (A) (void)hipFree(A);
+    if (B) (void)hipFree(B);
+    if (C) (void)hipFree(C);
+    if (ws) (void)hipFree(ws);
+    if (rc != GEMM_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table[Key(mode, m, n, k)] = {best_c, best_s};
+    return GEMM_OK;
+}
+
+}  // extern "C"

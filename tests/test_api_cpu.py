@@ -1,0 +1,153 @@
+"""The C-ABI library without a GPU: it loads, exports every declared entry
+point, and rejects bad arguments before making any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1306_6192_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mi355gemm.h")
+
+# Fake device addresses: validation never dereferences them.
+A_PTR, B_PTR, C_PTR = 0x10000000, 0x20000000, 0x30000000
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gemm_\w+)\s*\(", text)))
+
+
+def test_library_loads_without_gpu():
+    lib = _lib.load()
+    assert lib.gemm_version() >= 1
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding covers every one of them
+    assert set(names) <= set(_lib._SIGS), set(names) - set(_lib._SIGS)
+
+
+def _prob(**kw):
+    d = dict(mode=0, m=4, n=5, k=6, A=A_PTR, lda=6, B=B_PTR, ldb=5, C=C_PTR, ldc=5)
+    d.update(kw)
+    return _lib.problem(d["mode"], d["m"], d["n"], d["k"], d["A"], d["lda"], d["B"], d["ldb"], d["C"], d["ldc"],
+                        d.get("scale_a", 1.0), d.get("scale_b", 1.0), d.get("flags", 0))
+
+
+BAD = [
+    (dict(m=-1), "negative"),
+    (dict(k=-2), "negative"),
+    (dict(lda=5), "lda"),
+    (dict(ldb=4), "ldb"),
+    (dict(ldc=4), "ldc"),
+    (dict(mode=7), "mode"),
+    (dict(mode=-1), "mode"),
+    (dict(flags=1), "flags"),
+    (dict(C=None), "C is NULL"),
+    (dict(A=None), "NULL"),
+    (dict(B=None), "NULL"),
+    (dict(mode=3, scale_a=0.0), "scale"),
+    (dict(mode=3, scale_b=float("inf")), "scale"),
+    (dict(mode=3, scale_a=-1.0), "scale"),
+    (dict(C=A_PTR + 8), "overlap"),
+    (dict(C=B_PTR - 16), "overlap"),
+]
+
+
+@pytest.mark.parametrize("kw,msg", BAD)
+def test_plain_rejects_bad_arguments(kw, msg):
+    lib = _lib.load()
+    p = _prob(**kw)
+    rc = lib.gemm_plain(ctypes.byref(p), None)
+    assert rc == _lib.GEMM_EINVAL
+    assert msg.lower() in _lib.last_error().lower()
+    rc = lib.gemm_plain_cfg(ctypes.byref(p), 0, 1, None)
+    assert rc == _lib.GEMM_EINVAL
+
+
+def test_plain_cfg_rejects_bad_config_and_split():
+    lib = _lib.load()
+    p = _prob()
+    assert lib.gemm_plain_cfg(ctypes.byref(p), 0, 0, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_plain_cfg(ctypes.byref(p), 999, 1, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_plain_cfg(ctypes.byref(p), -1, 1, None) == _lib.GEMM_EINVAL
+
+
+def test_empty_output_is_a_noop_without_gpu():
+    lib = _lib.load()
+    for kw in (dict(m=0, A=None, C=None), dict(n=0, ldb=1, ldc=1, B=None, C=None)):
+        p = _prob(**kw)
+        assert lib.gemm_plain(ctypes.byref(p), None) == _lib.GEMM_OK, _lib.last_error()
+
+
+def test_null_problem_pointer():
+    lib = _lib.load()
+    assert lib.gemm_plain(None, None) == _lib.GEMM_EINVAL
+
+
+def test_config_tables():
+    lib = _lib.load()
+    n = lib.gemm_num_configs(0)
+    assert n >= 4
+    info = (ctypes.c_int32 * 6)()
+    seen = set()
+    for c in range(n):
+        assert lib.gemm_config_info(0, c, info) == 0
+        bm, bn, bk, waves, lds, mk = list(info)
+        assert bm % 32 == 0 and bn % 32 == 0 and bk == 32 and waves == 4 and 0 < lds <= 160 * 1024
+        seen.add((bm, bn))
+    assert len(seen) == n
+    assert lib.gemm_config_info(0, n, info) == _lib.GEMM_EINVAL
+    assert lib.gemm_num_configs(9) == _lib.GEMM_EINVAL
+
+
+def test_tuner_lookup_is_a_pure_function_of_shape(tmp_path):
+    lib = _lib.load()
+    c1, s1, c2, s2 = (ctypes.c_int32() for _ in range(4))
+    assert lib.gemm_tuner_lookup(0, 8192, 8192, 8192, ctypes.byref(c1), ctypes.byref(s1)) == 0
+    assert lib.gemm_tuner_lookup(0, 8192, 8192, 8192, ctypes.byref(c2), ctypes.byref(s2)) == 0
+    assert (c1.value, s1.value) == (c2.value, s2.value)
+    assert s1.value == 1
+    # a skinny shape with few output tiles asks for split-K or small tiles
+    assert lib.gemm_tuner_lookup(0, 128, 8192, 8192, ctypes.byref(c1), ctypes.byref(s1)) == 0
+    info = (ctypes.c_int32 * 6)()
+    lib.gemm_config_info(0, c1.value, info)
+    tiles = -(-128 // info[0]) * -(-8192 // info[1]) * s1.value
+    assert tiles >= 128
+    # save/load round trip of an (empty or filled) table
+    path = str(tmp_path / "tune.jsonl").encode()
+    assert lib.gemm_tuner_save(path) == 0
+    assert lib.gemm_tuner_load(path) == 0
+    assert lib.gemm_tuner_load(b"/nonexistent/file") == _lib.GEMM_ENOTFOUND
+
+
+def test_tuner_file_entries_override(tmp_path):
+    lib = _lib.load()
+    path = tmp_path / "t.jsonl"
+    path.write_text('{"mode": 0, "m": 333, "n": 444, "k": 555, "cfg": 3, "split": 2}\n'
+                    'garbage line\n'
+                    '{"mode": 0, "m": 1, "n": 1, "k": 1, "cfg": 999, "split": 1}\n')
+    assert lib.gemm_tuner_load(str(path).encode()) == 0
+    c, s = ctypes.c_int32(), ctypes.c_int32()
+    lib.gemm_tuner_lookup(0, 333, 444, 555, ctypes.byref(c), ctypes.byref(s))
+    assert (c.value, s.value) == (3, 2)
+
+
+def test_misc_entry_points_validate():
+    lib = _lib.load()
+    assert lib.gemm_convert_f32(None, -1, 1, None, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_convert_f32(A_PTR, 10, 0, B_PTR, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_convert_f32(A_PTR, 10, 1, A_PTR + 8, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_convert_f32(None, 0, 1, None, None) == _lib.GEMM_OK
+    assert lib.gemm_quantize_e4m3(A_PTR, 10, B_PTR, None, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_errnorm(A_PTR, 3, B_PTR, 3, 2, 4, C_PTR, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_errnorm(A_PTR, 4, B_PTR, 4, 2, 4, None, None) == _lib.GEMM_EINVAL
