@@ -191,6 +191,12 @@ int gemm_serve_drain(void *server);
 int gemm_serve_stats(void *server, gemm_serve_stats_t *out);
 /* Drains, then frees the server. */
 int gemm_serve_destroy(void *server);
+/* Open-loop load generator: submit ps[i] when the steady clock reaches
+ * t0 + offsets_ns[i] (t0 = the call time) with that scheduled time as its
+ * arrival stamp, retrying while the queue is full; tickets_out[i] receives
+ * its ticket.  Returns once every request is submitted. */
+int gemm_serve_replay(void *server, const gemm_problem_t *ps, const uint64_t *offsets_ns, int32_t count,
+                      uint64_t *tickets_out);
 /* Current steady-clock time in ns (the clock of the serving timestamps). */
 uint64_t gemm_now_ns(void);
 

@@ -89,6 +89,7 @@ _SIGS = {
     "gemm_serve_submit": (c_int32, [c_void_p, _P, c_uint64, POINTER(c_uint64)]),
     "gemm_serve_poll": (c_int32, [c_void_p, c_uint64, POINTER(ServeResult)]),
     "gemm_serve_drain": (c_int32, [c_void_p]),
+    "gemm_serve_replay": (c_int32, [c_void_p, _P, POINTER(c_uint64), c_int32, POINTER(c_uint64)]),
     "gemm_serve_stats": (c_int32, [c_void_p, POINTER(ServeStats)]),
     "gemm_serve_destroy": (c_int32, [c_void_p]),
     "gemm_now_ns": (c_uint64, []),

@@ -1,0 +1,21 @@
+// F16 product kernels: the plain launch for every tile configuration and
+// the grouped persistent launch (128x128 and 64x64 tiles).
+#include "kernels_impl.hpp"
+#include "tile_lp.hpp"
+
+static const KernelCfg kTable[] = {
+    make_cfg<LpCfg<GEMM_MODE_F16, 256, 256>, 1>(), make_cfg<LpCfg<GEMM_MODE_F16, 256, 128>, 1>(),
+    make_cfg<LpCfg<GEMM_MODE_F16, 128, 256>, 1>(), make_cfg<LpCfg<GEMM_MODE_F16, 128, 128>, 2>(),
+    make_cfg<LpCfg<GEMM_MODE_F16, 128, 64>, 2>(),  make_cfg<LpCfg<GEMM_MODE_F16, 64, 128>, 2>(),
+    make_cfg<LpCfg<GEMM_MODE_F16, 64, 64>, 4>(),
+};
+
+const KernelCfg *lp_configs_f16(int *count) {
+    *count = (int)(sizeof(kTable) / sizeof(kTable[0]));
+    return kTable;
+}
+
+static const GroupedKernel kGrouped = {
+    {3, 6}, 2, launch_grouped_t<LpCfg<GEMM_MODE_F16, 128, 128>, LpCfg<GEMM_MODE_F16, 64, 64>, 2>};
+
+const GroupedKernel *lp_grouped_f16() { return &kGrouped; }

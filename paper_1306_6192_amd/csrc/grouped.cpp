@@ -1,0 +1,229 @@
+// Grouped product: many independent problems in one persistent launch, and
+// its capture into a HIP graph.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+
+#include "grouped.hpp"
+
+namespace mg {
+
+// Per-problem choice between the grouped kernel's two tile configurations:
+// the cost model weighs the padded tile area against the lower sustained rate
+// of the small tile.
+int grouped_choose(int mode, int64_t m, int64_t n, int64_t k) {
+    (void)k;
+    const GroupedKernel *gk = grouped_kernel(mode);
+    int count = 0;
+    const KernelCfg *t = configs(mode, &count);
+    double best = 1e300;
+    int pick = 0;
+    for (int c = 0; c < 2; ++c) {
+        const KernelCfg &kc = t[gk->cfg_idx[c]];
+        const double tiles = (double)((m + kc.bm - 1) / kc.bm) * (double)((n + kc.bn - 1) / kc.bn);
+        const double eff = (kc.bm * kc.bn >= 16384) ? 1.0 : 0.6;
+        const double cost = tiles * kc.bm * kc.bn / eff;
+        if (cost < best * 0.999) {
+            best = cost;
+            pick = c;
+        }
+    }
+    return pick;
+}
+
+const GroupedKernel *grouped_kernel(int mode) {
+    if (mode == GEMM_MODE_F32) return f32_grouped();
+    return lp_grouped(mode);
+}
+
+int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan) {
+    if (count < 0) return fail(GEMM_EINVAL, "negative problem count");
+    if (count > 0 && !ps) return fail(GEMM_EINVAL, "problem array is NULL");
+    plan.descs.clear();
+    plan.total_tiles = 0;
+    plan.mode = count > 0 ? ps[0].mode : GEMM_MODE_F32;
+    for (int i = 0; i < count; ++i) {
+        int rc = validate(&ps[i]);
+        if (rc != GEMM_OK) {
+            char why[256];
+            snprintf(why, sizeof(why), "%s", gemm_last_error());
+            return fail(rc, "problem %d: %s", i, why);
+        }
+        if (ps[i].mode != plan.mode) return fail(GEMM_EINVAL, "problem %d: all problems must share one mode", i);
+    }
+    plan.gk = grouped_kernel(plan.mode);
+    if (!plan.gk) return fail(GEMM_EUNSUPPORTED, "mode %d has no grouped kernel", plan.mode);
+    int tcount = 0;
+    const KernelCfg *t = configs(plan.mode, &tcount);
+    struct Item {
+        GroupDesc d;
+        double cost;
+        int tiles;
+    };
+    std::vector<Item> items;
+    items.reserve(count);
+    for (int i = 0; i < count; ++i) {
+        const gemm_problem_t &p = ps[i];
+        if (p.m == 0 || p.n == 0) continue;
+        Item it;
+        memset(&it.d, 0, sizeof(it.d));
+        it.d.cfg = grouped_choose(p.mode, p.m, p.n, p.k);
+        const KernelCfg &kc = t[plan.gk->cfg_idx[it.d.cfg]];
+        it.d.P = make_launch(p, kc, 1).P;
+        it.tiles = it.d.P.tiles_m * it.d.P.tiles_n;
+        it.cost = (double)kc.bm * kc.bn * (double)std::max<int64_t>(p.k, 1);
+        items.push_back(it);
+    }
+    // Longest tiles first: workgroups take tiles round-robin, so each round of
+    // gridDim tiles is of similar cost.
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+    int64_t start = 0;
+    for (auto &it : items) {
+        it.d.tile_start = (int32_t)start;
+        start += it.tiles;
+        if (start > INT32_MAX) return fail(GEMM_EUNSUPPORTED, "grouped launch above 2^31 tiles");
+        plan.descs.push_back(it.d);
+    }
+    plan.total_tiles = (int)start;
+    plan.nwg = (int)std::min<int64_t>(start, (int64_t)num_cus() * plan.gk->wg_per_cu);
+    return GEMM_OK;
+}
+
+int enqueue_group(const GroupPlan &plan, const GroupDesc *dev_descs, hipStream_t s) {
+    if (plan.total_tiles == 0) return GEMM_OK;
+    GroupedArgs G;
+    G.descs = dev_descs;
+    G.count = (int32_t)plan.descs.size();
+    G.total_tiles = plan.total_tiles;
+    MG_HIP(plan.gk->launch(G, plan.nwg, s));
+    return GEMM_OK;
+}
+
+// Pinned host staging for descriptor uploads, one per stream; an event marks
+// when the previous upload from it has finished.
+struct HostStage {
+    void *host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+};
+static std::mutex g_stage_mu;
+static std::map<std::pair<int, hipStream_t>, HostStage *> g_stage;
+
+int upload_descs(const GroupPlan &plan, hipStream_t s, const GroupDesc **dev_out) {
+    const size_t bytes = plan.descs.size() * sizeof(GroupDesc);
+    DevBuf *db = stream_workspace(s, 1);
+    int rc = db->ensure(std::max<size_t>(bytes, 256), s);
+    if (rc != GEMM_OK) return rc;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    HostStage *st;
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        HostStage *&p = g_stage[{dev, s}];
+        if (!p) p = new HostStage();
+        st = p;
+    }
+    if (st->ev) MG_HIP(hipEventSynchronize(st->ev));
+    else MG_HIP(hipEventCreateWithFlags(&st->ev, hipEventDisableTiming));
+    if (st->bytes < bytes) {
+        if (st->host) MG_HIP(hipHostFree(st->host));
+        st->host = nullptr;
+        st->bytes = 0;
+        MG_HIP(hipHostMalloc(&st->host, std::max<size_t>(bytes, 4096), hipHostMallocDefault));
+        st->bytes = std::max<size_t>(bytes, 4096);
+    }
+    memcpy(st->host, plan.descs.data(), bytes);
+    MG_HIP(hipMemcpyAsync(db->ptr, st->host, bytes, hipMemcpyHostToDevice, s));
+    MG_HIP(hipEventRecord(st->ev, s));
+    *dev_out = static_cast<const GroupDesc *>(db->ptr);
+    return GEMM_OK;
+}
+
+struct GroupGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *descs = nullptr;
+};
+
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+int gemm_grouped(const gemm_problem_t *ps, int32_t count, void *stream) {
+    clear_error();
+    GroupPlan plan;
+    int rc = build_group_plan(ps, count, plan);
+    if (rc != GEMM_OK || plan.total_tiles == 0) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const GroupDesc *dd = nullptr;
+    rc = upload_descs(plan, s, &dd);
+    if (rc != GEMM_OK) return rc;
+    return enqueue_group(plan, dd, s);
+}
+
+int gemm_grouped_graph_create(const gemm_problem_t *ps, int32_t count, void **graph_out) {
+    clear_error();
+    if (!graph_out) return fail(GEMM_EINVAL, "graph_out is NULL");
+    *graph_out = nullptr;
+    GroupPlan plan;
+    int rc = build_group_plan(ps, count, plan);
+    if (rc != GEMM_OK) return rc;
+    GroupGraph *g = new GroupGraph();
+    if (plan.total_tiles > 0) {
+        const size_t bytes = plan.descs.size() * sizeof(GroupDesc);
+        hipStream_t cs = nullptr;
+        hipError_t e = hipMalloc(&g->descs, bytes);
+        if (e == hipSuccess) e = hipMemcpy(g->descs, plan.descs.data(), bytes, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = enqueue_group(plan, static_cast<const GroupDesc *>(g->descs), cs);
+            hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+            if (rc == GEMM_OK && e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess && rc == GEMM_OK) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (e != hipSuccess || rc != GEMM_OK) {
+            if (g->exec) (void)hipGraphExecDestroy(g->exec);
+            if (g->graph) (void)hipGraphDestroy(g->graph);
+            if (g->descs) (void)hipFree(g->descs);
+            delete g;
+            if (rc != GEMM_OK) return rc;
+            return fail(GEMM_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+        }
+    }
+    *graph_out = g;
+    return GEMM_OK;
+}
+
+int gemm_graph_launch(void *graph, void *stream) {
+    clear_error();
+    if (!graph) return fail(GEMM_EINVAL, "graph is NULL");
+    GroupGraph *g = static_cast<GroupGraph *>(graph);
+    if (!g->exec) return GEMM_OK;  // an empty group
+    MG_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return GEMM_OK;
+}
+
+int gemm_graph_destroy(void *graph) {
+    clear_error();
+    if (!graph) return fail(GEMM_EINVAL, "graph is NULL");
+    GroupGraph *g = static_cast<GroupGraph *>(graph);
+    if (g->exec) {
+        // replays may still be running on some stream: wait before freeing
+        (void)hipDeviceSynchronize();
+        (void)hipGraphExecDestroy(g->exec);
+    }
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->descs) (void)hipFree(g->descs);
+    delete g;
+    return GEMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,30 @@
+// Grouped-launch planning, shared by the grouped entry points and the
+// serving runtime.
+#pragma once
+
+#include "host.hpp"
+
+namespace mg {
+
+struct GroupPlan {
+    int mode = 0;
+    const GroupedKernel *gk = nullptr;
+    std::vector<GroupDesc> descs;   // sorted by descending per-tile cost
+    int total_tiles = 0;
+    int nwg = 0;
+};
+
+const GroupedKernel *grouped_kernel(int mode);
+int grouped_choose(int mode, int64_t m, int64_t n, int64_t k);
+
+// Validate the problems (one mode), choose each problem's tile configuration
+// and lay the tiles out; empty outputs are dropped.
+int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan);
+
+// Copy the descriptors to the stream's device workspace (stream-ordered).
+int upload_descs(const GroupPlan &plan, hipStream_t s, const GroupDesc **dev_out);
+
+// Launch the persistent kernel over descriptors already on the device.
+int enqueue_group(const GroupPlan &plan, const GroupDesc *dev_descs, hipStream_t s);
+
+}  // namespace mg

@@ -7,7 +7,8 @@
 struct GroupDesc {
     TileProblem P;        // splits == 1
     int32_t tile_start;   // first global tile index of this problem
-    int32_t pad[3];
+    int32_t cfg;          // 0 or 1: which of the grouped kernel's two tile configurations
+    int32_t pad[2];
 };
 
 struct GroupedArgs {
@@ -21,15 +22,25 @@ typedef hipError_t (*GroupedLaunchFn)(const GroupedArgs &G, int nwg, hipStream_t
 
 struct KernelCfg {
     int bm, bn, bk, waves, lds_bytes, mfma_k;
-    int wg_per_cu;             // resident workgroups per CU used to size persistent grids
+    int wg_per_cu;             // resident workgroups per CU (register and LDS limits)
     PlainLaunchFn plain;
-    GroupedLaunchFn grouped;
+};
+
+// The grouped kernel of a mode: two tile configurations (indices into the
+// mode's plain table, so a problem gets the same tiles -- and bits -- as a
+// plain launch of that configuration).
+struct GroupedKernel {
+    int cfg_idx[2];
+    int wg_per_cu;
+    GroupedLaunchFn launch;
 };
 
 // Tables of the configurations compiled for each mode (defined in the
 // per-mode translation units).
 const KernelCfg *f32_configs(int *count);
 const KernelCfg *lp_configs(int mode, int *count);
+const GroupedKernel *f32_grouped();
+const GroupedKernel *lp_grouped(int mode);
 
 // Elementwise / reduction kernels (misc.hip).
 hipError_t launch_fill_zero(float *C, int64_t ldc, int m, int n, hipStream_t s);

@@ -1,0 +1,75 @@
+// Kernel templates shared by every mode: the plain launch (one output tile
+// per workgroup, XCD-aware tile order) and the grouped persistent launch
+// (workgroups walk the tiles of many problems, each problem with one of two
+// tile configurations).
+#pragma once
+
+#include "kernels.hpp"
+
+template <class Cfg, int OCC>
+__global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_plain_kernel(TileProblem P) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[Cfg::LDS_BYTES];
+    const int per_split = P.tiles_m * P.tiles_n;
+    int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int split = t / per_split;
+    t -= split * per_split;
+    int tm, tn;
+    tile_coords(t, P.tiles_m, P.tiles_n, 8, tm, tn);
+    Cfg::run(P, tm, tn, split, lds);
+}
+
+// Locate the problem that owns global tile t (descriptors sorted by
+// tile_start, binary search).
+__device__ __forceinline__ int group_find(const GroupDesc *d, int count, int t) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile_start <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int A, int B> struct cmax { static constexpr int v = A > B ? A : B; };
+
+// Each workgroup takes tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... of
+// the concatenated tile lists; descriptor field `cfg` selects Cfg0 or Cfg1 for
+// that problem.  Every workgroup leaves the loop after the last tile, so the
+// grid always drains.
+template <class Cfg0, class Cfg1, int OCC>
+__global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_grouped_kernel(GroupedArgs G) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[cmax<Cfg0::LDS_BYTES, Cfg1::LDS_BYTES>::v];
+    for (int t = blockIdx.x; t < G.total_tiles; t += gridDim.x) {
+        const int p = group_find(G.descs, G.count, t);
+        const GroupDesc &d = G.descs[p];
+        const TileProblem P = d.P;
+        const int local = t - d.tile_start;
+        int tm, tn;
+        if (d.cfg == 0) {
+            tile_coords(local, P.tiles_m, P.tiles_n, 8, tm, tn);
+            Cfg0::run(P, tm, tn, 0, lds);
+        } else {
+            tile_coords(local, P.tiles_m, P.tiles_n, 8, tm, tn);
+            Cfg1::run(P, tm, tn, 0, lds);
+        }
+    }
+}
+
+template <class Cfg, int OCC>
+static hipError_t launch_plain_t(const TileProblem &P, int nwg, hipStream_t s) {
+    hipLaunchKernelGGL((gemm_plain_kernel<Cfg, OCC>), dim3(nwg), dim3(GEMM_THREADS), 0, s, P);
+    return hipGetLastError();
+}
+
+template <class Cfg0, class Cfg1, int OCC>
+static hipError_t launch_grouped_t(const GroupedArgs &G, int nwg, hipStream_t s) {
+    hipLaunchKernelGGL((gemm_grouped_kernel<Cfg0, Cfg1, OCC>), dim3(nwg), dim3(GEMM_THREADS), 0, s, G);
+    return hipGetLastError();
+}
+
+template <class Cfg, int OCC>
+constexpr KernelCfg make_cfg() {
+    return KernelCfg{Cfg::BM, Cfg::BN, Cfg::BK, 4, Cfg::LDS_BYTES, Cfg::MFMA_K,
+                     (160 * 1024 / Cfg::LDS_BYTES) < OCC ? (160 * 1024 / Cfg::LDS_BYTES) : OCC,
+                     launch_plain_t<Cfg, OCC>};
+}

@@ -28,7 +28,7 @@
 // output column CB*jj + cb, and the epilogue stores CB consecutive floats.
 #pragma once
 
-#include "common.hpp"
+#include "tile_common.hpp"
 
 template <int BM_, int BN_>
 struct F32Cfg {
@@ -47,6 +47,8 @@ struct F32Cfg {
     static_assert(RB >= 1 && (CB == 1 || CB == 2 || CB == 4), "wave tile");
     static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+    static constexpr int MFMA_K = 2;
+    __device__ static void run(const TileProblem &P, int tm, int tn, int split, uint8_t *lds);
 };
 
 template <int CB> struct FVec;
@@ -55,14 +57,15 @@ template <> struct FVec<2> { typedef f32x2 T; };
 template <> struct FVec<4> { typedef f32x4 T; };
 
 // Four consecutive floats of row r starting at column c, zero outside
-// [0,R) x [0,Cn).  `vec` promises 16-B alignment of every row start.
-__device__ __forceinline__ f32x4 f32_load4(const float *__restrict__ P, int64_t ld, int r, int c,
-                                           int R, int Cn, bool vec) {
+// [0,R) x [0,Cn).  Rows may start at any 4-byte address.
+__device__ __forceinline__ f32x4 f32_load4(const float *__restrict__ P, int64_t ld, int r, int c, int R,
+                                           int Cn) {
     f32x4 v = {0.f, 0.f, 0.f, 0.f};
     if (r < R) {
         const float *p = P + (int64_t)r * ld + c;
-        if (vec && c + 3 < Cn) {
-            v = *reinterpret_cast<const f32x4 *>(p);
+        if (c + 3 < Cn) {
+            const u32x4 u = ld16(p);
+            v = __builtin_bit_cast(f32x4, u);
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
@@ -83,14 +86,14 @@ __device__ __forceinline__ void f32_load_tiles(const TileProblem &P, int m0, int
         const int idx = tid + q * GEMM_THREADS;
         const int r = idx / (Cfg::BK / 4);
         const int kv = (idx % (Cfg::BK / 4)) * 4;
-        ra[q] = f32_load4(A, P.lda, m0 + r, k0 + kv, P.m, P.k, P.vec & 1);
+        ra[q] = f32_load4(A, P.lda, m0 + r, k0 + kv, P.m, P.k);
     }
 #pragma unroll
     for (int q = 0; q < Cfg::BV; ++q) {
         const int idx = tid + q * GEMM_THREADS;
         const int kr = idx / (Cfg::BN / 4);
         const int cv = (idx % (Cfg::BN / 4)) * 4;
-        rb[q] = f32_load4(B, P.ldb, k0 + kr, n0 + cv, P.k, P.n, P.vec & 2);
+        rb[q] = f32_load4(B, P.ldb, k0 + kr, n0 + cv, P.k, P.n);
     }
 }
 
@@ -151,52 +154,6 @@ __device__ __forceinline__ void f32_compute_stage(const float *stage, f32x16 (&a
     }
 }
 
-// Store the accumulators of one tile to C (or to a split-K partial slab).
-// Lane l, block (rb, cb), register r holds row 8*(r/4) + 4*(l/32) + r%4 of
-// the block and output column CB*(l%32) + cb of the wave's columns.
-template <class Cfg>
-__device__ __forceinline__ void f32_epilogue(float *__restrict__ C, int64_t ldc, int M, int N,
-                                             int m0, int n0, bool vec, float scale,
-                                             const f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
-    const int l32 = lane & 31, g = lane >> 5;
-    const int col = n0 + wn * Cfg::TN + Cfg::CB * l32;
-    const bool full_cols = vec && (col + Cfg::CB <= N);
-#pragma unroll
-    for (int rb = 0; rb < Cfg::RB; ++rb) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = m0 + wm * Cfg::TM + rb * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-            if (row >= M) continue;
-            float *p = C + (int64_t)row * ldc + col;
-            if constexpr (Cfg::CB == 4) {
-                f32x4 v = {acc[rb][0][r] * scale, acc[rb][1][r] * scale, acc[rb][2][r] * scale,
-                           acc[rb][3][r] * scale};
-                if (full_cols) {
-                    *reinterpret_cast<f32x4 *>(p) = v;
-                    continue;
-                }
-#pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-                    if (col + cb < N) p[cb] = v[cb];
-            } else if constexpr (Cfg::CB == 2) {
-                f32x2 v = {acc[rb][0][r] * scale, acc[rb][1][r] * scale};
-                if (full_cols) {
-                    *reinterpret_cast<f32x2 *>(p) = v;
-                    continue;
-                }
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-                    if (col + cb < N) p[cb] = v[cb];
-            } else {
-                if (col < N) p[0] = acc[rb][0][r] * scale;
-            }
-        }
-    }
-}
-
 // One BM x BN output tile over the k-tiles of split `split`.
 template <class Cfg>
 __device__ __forceinline__ void f32_tile(const TileProblem &P, int tm, int tn, int split, float *lds) {
@@ -228,14 +185,14 @@ __device__ __forceinline__ void f32_tile(const TileProblem &P, int tm, int tn, i
         __syncthreads();
     }
 
-    float *C = P.C;
-    int64_t ldc = P.ldc;
-    bool vec = (P.vec & 4) != 0;
-    if (P.splits > 1) {
-        C = P.C + (int64_t)split * P.split_stride;
-        ldc = P.n;
-        vec = (P.n % 4) == 0;
-    }
-    // Split-K partials are stored unscaled; the reduction applies the scale.
-    f32_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, vec, P.splits > 1 ? 1.f : P.scale, acc);
+    float *C;
+    int64_t ldc;
+    float scale;
+    epilogue_target(P, split, C, ldc, scale);
+    tile_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
+}
+
+template <int BM, int BN>
+__device__ __forceinline__ void F32Cfg<BM, BN>::run(const TileProblem &P, int tm, int tn, int split, uint8_t *lds) {
+    f32_tile<F32Cfg<BM, BN>>(P, tm, tn, split, reinterpret_cast<float *>(lds));
 }

@@ -1,0 +1,224 @@
+"""Parity of the reduced-precision forms (BF16, F16, FP8 E4M3, split-BF16x3)
+with the binary64 oracle, through the C-ABI.
+
+Two references per product:
+* the secondary oracle -- the exact product of the quantised operands (for
+  split-BF16x3: hiA hiB + hiA loB + loA hiB) in binary64.  Every product of
+  two quantised values is exact in float32, so the kernel may differ from it
+  only by float32 accumulation: each element within (terms + 2) u32
+  (|A||B|)_ij -- plus, for FP8, the loss of the instruction's own grouped
+  summation (see FP8_KEEP_BITS below);
+* the oracle of record -- the binary64 product of the float32 sources: the
+  normwise error must sit inside the band of the format (bounds from the
+  format's unit roundoff; split-BF16x3 must reach float32-level 1e-5).
+Integer-valued inputs exactly representable in each format must match the
+oracle bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import formats as F
+from tests._gpu import U32, abs_product, dev, host, log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1306_6192_amd as mg  # noqa: E402
+
+MODES = [mg.MODE_BF16, mg.MODE_F16, mg.MODE_F8E4M3, mg.MODE_SPLIT_BF16X3]
+# normwise error of record, N(0,1) inputs: a few units of the format's
+# unit roundoff (bf16 2^-8, f16 2^-11, e4m3 2^-4 with amax scaling)
+BAND = {mg.MODE_BF16: 8e-3, mg.MODE_F16: 1e-3, mg.MODE_F8E4M3: 8e-2, mg.MODE_SPLIT_BF16X3: 1e-5}
+
+
+def quantise_host(X, mode):
+    """Oracle-side operand preparation: (codes or float32, exact binary64 values, scale)."""
+    if mode == mg.MODE_BF16:
+        b = F.to_bf16_bits(X)
+        return b, F.decode(b, "bf16"), 1.0
+    if mode == mg.MODE_F16:
+        b = F.to_f16_bits(X)
+        return b, F.decode(b, "f16"), 1.0
+    if mode == mg.MODE_F8E4M3:
+        s = F.e4m3_scale(X)
+        b = F.to_e4m3_bits(X, s)
+        return b, F.decode(b, "e4m3"), float(s)
+    return X, None, 1.0
+
+
+def device_operands(A, B, mode):
+    """Product-path operand preparation on the GPU (conversion kernels)."""
+    dA, dB = dev(A), dev(B)
+    if mode in (mg.MODE_BF16, mg.MODE_F16):
+        return mg.convert(dA, mode), mg.convert(dB, mode), 1.0, 1.0
+    if mode == mg.MODE_F8E4M3:
+        qa, sa = mg.quantize_e4m3(dA)
+        qb, sb = mg.quantize_e4m3(dB)
+        return qa, qb, float(host(sa)[0]), float(host(sb)[0])
+    return dA, dB, 1.0, 1.0
+
+
+def secondary(A, B, mode):
+    """(reference, |A||B| weight, number of float32-rounded terms per element,
+    extra bound term of the FP8 instruction's grouped summation)."""
+    k = A.shape[1]
+    if mode == mg.MODE_SPLIT_BF16X3:
+        R = oracle.gemm_split_bf16x3(A, B)
+        return R, abs_product(A, B) * 1.01, 3 * k, 0.0
+    qa, va, sa = quantise_host(A, mode)
+    qb, vb, sb = quantise_host(B, mode)
+    R = oracle.gemm(va, vb) * (sa * sb)
+    extra = fp8_group_term(va, vb) * (sa * sb) if mode == mg.MODE_F8E4M3 else 0.0
+    return R, abs_product(va, vb) * (sa * sb), k, extra
+
+
+def check_bound(C, R, W, terms, what, extra=0.0):
+    err = np.abs(C.astype(np.float64) - R)
+    bound = (terms + 2) * U32 * W + extra + 2 * U32 * np.abs(R) + 1e-30
+    assert np.all(err <= bound), f"{what}: max err/bound {np.max(err / bound):.3f}"
+
+
+# The FP8 matrix instruction does not sum its 64 products in float32: it adds
+# them in groups of 8 consecutive k, each product aligned to the largest
+# product exponent E of its group and cut to 13 fraction bits below 2^E
+# (measured on the device: 1 + 2^-13 survives, 1 +- 2^-14 does not; a 2^-18
+# term in another group of 8 survives).  The largest product of a group is
+# exact, so a group loses less than 7 * 2^-13 * max_group |p|.
+FP8_GROUP = 8
+FP8_KEEP_BITS = 13
+
+
+def fp8_group_term(va, vb):
+    """sum over groups of 8 consecutive k of max |a_ir b_rj| (m x n), times 7 * 2^-13."""
+    m, k = va.shape
+    n = vb.shape[1]
+    G = np.zeros((m, n))
+    for r0 in range(0, k, FP8_GROUP):
+        gm = np.zeros((m, n))
+        for r in range(r0, min(k, r0 + FP8_GROUP)):
+            gm = np.maximum(gm, np.abs(va[:, r:r + 1] * vb[r:r + 1, :]))
+        G += gm
+    return 7 * 2.0 ** -FP8_KEEP_BITS * G
+
+
+def fp8_group_term_pairs(ar, bc):
+    """The same term for sampled (row i of ar) . (column i of bc) pairs."""
+    p = np.abs(ar * bc.T)                      # samples x k
+    k = p.shape[1]
+    pad = (-k) % FP8_GROUP
+    p = np.pad(p, ((0, 0), (0, pad)))
+    return 7 * 2.0 ** -FP8_KEEP_BITS * p.reshape(p.shape[0], -1, FP8_GROUP).max(axis=2).sum(axis=1)
+
+
+SHAPES = [(1, 1, 1), (7, 5, 3), (33, 31, 65), (64, 64, 64), (127, 129, 255), (129, 257, 100),
+          (255, 3, 513), (3, 255, 1000), (300, 200, 1), (97, 61, 4099)]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("m,n,k", SHAPES)
+def test_shapes_every_config(mode, m, n, k):
+    log(f"precision {mg.MODE_NAMES[mode]} shape {(m, n, k)}")
+    A, B = synth.pair(m, n, k, seed=m + 3 * n + 7 * k, dist="normal")
+    R, W, terms, extra = secondary(A, B, mode)
+    R64 = oracle.gemm(A, B)
+    a, b, sa, sb = device_operands(A, B, mode)
+    for cfg in range(mg.num_configs(mode)):
+        for split in (1, 3):
+            C = host(mg.gemm(a, b, mode=mode, scale_a=sa, scale_b=sb, cfg=cfg, split_k=split))
+            check_bound(C, R, W, terms, f"{mg.MODE_NAMES[mode]} {(m, n, k)} cfg {cfg} split {split}", extra)
+    if m * n >= 64 and k >= 64:
+        assert oracle.relerr(C, R64) <= BAND[mode]
+
+
+@pytest.mark.parametrize("mode,R_int", [(mg.MODE_BF16, 16), (mg.MODE_F16, 16), (mg.MODE_F8E4M3, 15),
+                                        (mg.MODE_SPLIT_BF16X3, 16)])
+def test_integer_inputs_bit_exact(mode, R_int):
+    """Integers up to R_int are exact in the format; k R^2 < 2^24 keeps every
+    float32 partial sum exact, in any order."""
+    log(f"precision {mg.MODE_NAMES[mode]} integer-exact")
+    m, n, k = 200, 300, 4096
+    A, B = synth.pair(m, n, k, seed=31, dist="integers", R=R_int)
+    R = oracle.gemm(A, B)
+    if mode == mg.MODE_F8E4M3:
+        a = dev(F.to_e4m3_bits(A, 1.0))
+        b = dev(F.to_e4m3_bits(B, 1.0))
+    elif mode in (mg.MODE_BF16, mg.MODE_F16):
+        a, b = mg.convert(dev(A), mode), mg.convert(dev(B), mode)
+    else:
+        a, b = dev(A), dev(B)
+    for cfg in range(mg.num_configs(mode)):
+        for split in (1, 4):
+            C = host(mg.gemm(a, b, mode=mode, cfg=cfg, split_k=split))
+            assert np.array_equal(C.astype(np.float64), R), (cfg, split)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_cross_config_bitwise_and_identity(mode):
+    log(f"precision {mg.MODE_NAMES[mode]} cross-config/identity")
+    A, B = synth.pair(190, 170, 333, seed=32, dist="normal")
+    a, b, sa, sb = device_operands(A, B, mode)
+    ref = host(mg.gemm(a, b, mode=mode, scale_a=sa, scale_b=sb, cfg=0, split_k=1))
+    for cfg in range(mg.num_configs(mode)):
+        assert np.array_equal(ref, host(mg.gemm(a, b, mode=mode, scale_a=sa, scale_b=sb, cfg=cfg, split_k=1)))
+    # identity: entries representable in the format come back unchanged
+    X = synth.draw(synth.rng(33), (150, 70), "wide_int")   # powers of two, |x| in [2^-8, 2^8]
+    if mode == mg.MODE_F8E4M3:
+        xa, ia = dev(F.to_e4m3_bits(X, 1.0)), dev(F.to_e4m3_bits(np.eye(70, dtype=np.float32), 1.0))
+    elif mode in (mg.MODE_BF16, mg.MODE_F16):
+        xa, ia = mg.convert(dev(X), mode), mg.convert(dev(np.eye(70, dtype=np.float32)), mode)
+    else:
+        xa, ia = dev(X), dev(np.eye(70, dtype=np.float32))
+    assert np.array_equal(host(mg.gemm(xa, ia, mode=mode)), X)
+
+
+LARGE = [(mode, dist) for mode in MODES for dist in ("normal", "wide")]
+
+
+@pytest.mark.parametrize("mode,dist", LARGE)
+def test_precision_sweep_8192_sampled(mode, dist):
+    """The precision workload at full size (m = n = k = 8192), as the benchmark
+    launches it: 512 sampled outputs against both references."""
+    log(f"precision {mg.MODE_NAMES[mode]} 8192^3 {dist}")
+    m = n = k = 8192
+    A, B = synth.pair(m, n, k, seed=0, dist=dist)
+    a, b, sa, sb = device_operands(A, B, mode)
+    C = host(mg.gemm(a, b, mode=mode, scale_a=sa, scale_b=sb))
+    del a, b
+    g = synth.rng(7)
+    rows = g.integers(0, m, size=512)
+    cols = g.integers(0, n, size=512)
+    Ar = A[rows]                       # 512 x k
+    Bc = np.ascontiguousarray(B[:, cols])  # k x 512
+    idx = np.arange(512)
+    R64 = oracle.gemm_sampled(Ar, Bc, idx, idx)
+    if mode == mg.MODE_SPLIT_BF16X3:
+        ah, al = (F.decode(x, "bf16") for x in F.split_bf16(Ar))
+        bh, bl = (F.decode(x, "bf16") for x in F.split_bf16(Bc))
+        R = (oracle.gemm_sampled(ah, bh, idx, idx) + oracle.gemm_sampled(ah, bl, idx, idx)
+             + oracle.gemm_sampled(al, bh, idx, idx))
+        W = np.sum(np.abs(Ar.astype(np.float64)) * np.abs(Bc.astype(np.float64)).T, axis=1) * 1.01
+        terms = 3 * k
+    else:
+        fmt = {mg.MODE_BF16: "bf16", mg.MODE_F16: "f16", mg.MODE_F8E4M3: "e4m3"}[mode]
+        if mode == mg.MODE_F8E4M3:
+            s_a, s_b = F.e4m3_scale(A), F.e4m3_scale(B)
+            assert (np.float32(sa), np.float32(sb)) == (s_a, s_b)
+            va = F.decode(F.to_e4m3_bits(Ar, s_a), fmt)
+            vb = F.decode(F.to_e4m3_bits(Bc, s_b), fmt)
+            sc = float(s_a) * float(s_b)
+        else:
+            va = F.decode(F.to_bf16_bits(Ar) if fmt == "bf16" else F.to_f16_bits(Ar), fmt)
+            vb = F.decode(F.to_bf16_bits(Bc) if fmt == "bf16" else F.to_f16_bits(Bc), fmt)
+            sc = 1.0
+        R = oracle.gemm_sampled(va, vb, idx, idx) * sc
+        W = np.sum(np.abs(va) * np.abs(vb).T, axis=1) * sc
+        terms = k
+        if mode == mg.MODE_F8E4M3:
+            W = W + fp8_group_term_pairs(va, vb) * sc / ((terms + 2) * U32)
+    got = C[rows, cols]
+    err = np.abs(got.astype(np.float64) - R)
+    bound = (terms + 2) * U32 * W + 2 * U32 * np.abs(R) + 1e-30
+    assert np.all(err <= bound), np.max(err / bound)
+    band = BAND[mode] * (3 if dist == "wide" else 1)
+    assert oracle.relerr(got, R64) <= band

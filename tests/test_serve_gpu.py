@@ -1,0 +1,127 @@
+"""Serving runtime on the GPU: a request's result is the same bits whether it
+runs alone or batched with others, in-flight memory stays within the budget,
+and results match the oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import formats as F
+from paper_1306_6192_amd import _lib
+from tests._gpu import U32, dev, host, log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1306_6192_amd as mg  # noqa: E402
+
+MIX = [mg.MODE_F32, mg.MODE_BF16, mg.MODE_F8E4M3]
+
+
+def build_requests(count, lo, hi, seed):
+    dims = synth.loguniform_dims(count, lo, hi, seed)
+    modes = synth.dtype_mix(count, seed=seed + 1)
+    g = synth.rng(seed + 2)
+    reqs = []
+    for (m, n, k), mi in zip(dims, modes):
+        m, n, k = int(m), int(n), int(k)
+        mode = MIX[int(mi)]
+        A = synth.draw(g, (m, k))
+        B = synth.draw(g, (k, n))
+        if mode == mg.MODE_F32:
+            a, b, sa, sb = dev(A), dev(B), 1.0, 1.0
+        elif mode == mg.MODE_BF16:
+            a, b, sa, sb = mg.convert(dev(A), mode), mg.convert(dev(B), mode), 1.0, 1.0
+        else:
+            a, qsa = mg.quantize_e4m3(dev(A))
+            b, qsb = mg.quantize_e4m3(dev(B))
+            sa, sb = float(host(qsa)[0]), float(host(qsb)[0])
+        C = torch.full((m, n), float("nan"), device="cuda")
+        reqs.append(dict(mode=mode, A=A, B=B, a=a, b=b, C=C, sa=sa, sb=sb,
+                         p=mg.make_problem(a, b, C, mode, sa, sb)))
+    torch.cuda.synchronize()
+    return reqs
+
+
+def run_server(reqs, offsets_ns=None, **kw):
+    cfg = dict(hbm_budget_bytes=4 << 30, max_inflight=256, num_streams=4, max_batch=32, queue_capacity=100000,
+               executor=0, fake_fail_every=0)
+    cfg.update(kw)
+    h = ctypes.c_void_p()
+    lib = _lib.load()
+    assert lib.gemm_serve_create(ctypes.byref(_lib.ServeConfig(**cfg)), ctypes.byref(h)) == 0, _lib.last_error()
+    n = len(reqs)
+    tickets = (ctypes.c_uint64 * n)()
+    arr = _lib.problems_array([r["p"] for r in reqs])
+    offs = np.zeros(n, np.uint64) if offsets_ns is None else np.asarray(offsets_ns, np.uint64)
+    assert lib.gemm_serve_replay(h, arr, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n, tickets) == 0
+    assert lib.gemm_serve_drain(h) == 0, _lib.last_error()
+    results = []
+    for i in range(n):
+        r = _lib.ServeResult()
+        assert lib.gemm_serve_poll(h, tickets[i], ctypes.byref(r)) == 0, _lib.last_error()
+        results.append(r)
+    s = _lib.ServeStats()
+    lib.gemm_serve_stats(h, ctypes.byref(s))
+    assert lib.gemm_serve_destroy(h) == 0
+    return results, s
+
+
+def test_alone_equals_in_the_mix_bitwise():
+    log("serve alone vs mix")
+    reqs = build_requests(48, 16, 700, seed=11)
+    alone = []
+    for r in reqs:
+        run_server([r])
+        alone.append(host(r["C"]).copy())
+        r["C"].fill_(float("nan"))
+    torch.cuda.synchronize()
+    res, st = run_server(reqs)
+    assert st.completed == len(reqs) and st.failed == 0
+    assert max(r.batch_size for r in res) > 1          # requests really were batched
+    for i, r in enumerate(reqs):
+        assert np.array_equal(host(r["C"]), alone[i]), i
+
+
+def test_results_match_oracle_and_budget_holds():
+    log("serve oracle + budget")
+    reqs = build_requests(40, 16, 400, seed=12)
+    fps = []
+    for r in reqs:
+        f = ctypes.c_uint64()
+        _lib.load().gemm_serve_footprint(ctypes.byref(r["p"]), ctypes.byref(f))
+        fps.append(f.value)
+    budget = 3 * max(fps)
+    offs = (synth.poisson_arrivals(len(reqs), 5000.0, seed=2) * 1e9).astype(np.uint64)
+    res, st = run_server(reqs, offs, hbm_budget_bytes=budget, max_batch=8, num_streams=2)
+    assert st.completed == len(reqs) and st.peak_inflight_bytes <= budget
+    for r in reqs:
+        C = host(r["C"])
+        if r["mode"] == mg.MODE_F32:
+            va, vb, sc = r["A"], r["B"], 1.0
+        elif r["mode"] == mg.MODE_BF16:
+            va, vb, sc = F.decode(F.to_bf16_bits(r["A"]), "bf16"), F.decode(F.to_bf16_bits(r["B"]), "bf16"), 1.0
+        else:
+            s_a, s_b = F.e4m3_scale(r["A"]), F.e4m3_scale(r["B"])
+            va = F.decode(F.to_e4m3_bits(r["A"], s_a), "e4m3")
+            vb = F.decode(F.to_e4m3_bits(r["B"], s_b), "e4m3")
+            sc = float(s_a) * float(s_b)
+        R = oracle.gemm(va, vb) * sc
+        W = (np.abs(np.asarray(va, np.float64)) @ np.abs(np.asarray(vb, np.float64))) * sc
+        k = r["A"].shape[1]
+        # FP8: the instruction's grouped summation keeps 13 bits below each
+        # group's largest product (bounded here by 2^-13 * 7 * W / 8 per group)
+        extra = 7 * 2.0 ** -13 * W if r["mode"] == mg.MODE_F8E4M3 else 0.0
+        assert np.all(np.abs(C - R) <= (k + 2) * U32 * W + extra + 2 * U32 * np.abs(R) + 1e-30)
+
+
+def test_plain_executor_equals_gemm_plain():
+    log("serve plain executor")
+    reqs = build_requests(24, 16, 600, seed=13)
+    run_server(reqs, executor=2, num_streams=1, max_batch=8)
+    for r in reqs:
+        got = host(r["C"]).copy()
+        ref = host(mg.gemm(r["a"], r["b"], mode=r["mode"], scale_a=r["sa"], scale_b=r["sb"]))
+        assert np.array_equal(got, ref)
