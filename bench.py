@@ -1,19 +1,32 @@
-"""Benchmark of the plain FP32 product on one MI355X.
+"""Benchmark of the dense product C = A*B on one MI355X.
 
-One step = one product of each plain FP32 workload shape, (m, n, k) in
-{2048^3, 4096^3, 8192^3, (8192, 1024, 4096), (128, 8192, 8192)}, entries
-uniform[-1, 1] from seed 0, inputs resident in HBM before the timed region.
-The line printed reports aggregate TFLOP/s over the step (2mnk flops per
-product), the roofline of the dominant launch (the 8192^3 product, timed with
-HIP events on the stream it runs on), the sampled normwise error of every
-shape against the binary64 oracle, and the oracle itself timed on the host's
-cores on a bounded sample (some rows of the 8192^3 product).
+Headline (the `value` of the printed line): the plain FP32 workload.  One
+step = one product of each shape (m, n, k) in {2048^3, 4096^3, 8192^3,
+(8192, 1024, 4096), (128, 8192, 8192)}, entries uniform[-1, 1] from seed 0,
+inputs resident in HBM before the timed region; value = aggregate TFLOP/s
+(2mnk flops per product).  The roofline object is for the dominant launch
+(8192^3), timed with HIP events on the stream it runs on.  Every shape's
+sampled normwise error against the binary64 oracle is reported, and the
+oracle itself is timed on the host's cores on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Secondary sections (extra keys of the same line; --sections to choose):
+  precision  m = n = k = 8192, N(0,1) and wide-range inputs: BF16, F16, FP8
+             E4M3 (per-tensor scale) and split-BF16x3, TFLOP/s, fraction of
+             the dtype's MFMA peak, sampled error vs the binary64 oracle.
+  grouped    512 problems, m, n, k log-uniform in [32, 1024] (seed 0), FP32
+             and BF16 in / FP32 out: one captured persistent launch vs 512
+             plain launches.
+  serving    Poisson arrivals of products with m, n, k log-uniform in
+             [64, 4096], 50% FP32 / 35% BF16 / 15% E4M3, operands resident
+             in HBM; p50/p99 latency and aggregate TFLOP/s per arrival rate,
+             continuous batching vs plain FIFO launches.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections plain,precision,grouped,serving]
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -26,7 +39,7 @@ sys.path.insert(0, ROOT)
 
 SHAPES = [(2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192), (8192, 1024, 4096), (128, 8192, 8192)]
 DOMINANT = (8192, 8192, 8192)
-PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK = {"f32": 157.3, "bf16": 2516.6, "f16": 2516.6, "e4m3": 5033.2}   # dense MFMA TFLOP/s
 
 
 def parse():
@@ -34,10 +47,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sections", default="plain,precision,grouped,serving")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
-    ap.add_argument("--samples", type=int, default=512, help="sampled outputs per shape for the error")
+    ap.add_argument("--samples", type=int, default=512, help="sampled outputs per product for the error")
+    ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--serve-rates", default="4000,16000,64000")
     return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def cpu_baseline(A, B, target_s: float):
@@ -52,8 +72,7 @@ def cpu_baseline(A, B, target_s: float):
     t0 = time.perf_counter()
     oracle.gemm(A[:rows].astype(np.float64), B64, threads)
     dt = time.perf_counter() - t0
-    total_rows = rows
-    total_t = dt
+    total_rows, total_t = rows, dt
     more = int(max(0, (target_s - dt) / max(dt, 1e-9) * rows))
     more = min(more, m - rows) // threads * threads
     if more > 0:
@@ -66,29 +85,34 @@ def cpu_baseline(A, B, target_s: float):
             "sample": f"{total_rows} full rows of the {m}x{n}x{k} product (binary64 loop), {total_t:.1f} s"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus above 1 is not supported"}))
-        sys.exit(2)
-    import torch
+class Timer:
+    """HIP-event timing of work enqueued on one stream."""
 
-    import paper_1306_6192_amd as mg
-    import synth
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
 
-    torch.cuda.set_device(0)
+    def time(self, fn, reps, warmup=1):
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in evs:
+            e0.record(self.stream)
+            fn()
+            e1.record(self.stream)
+        torch.cuda.synchronize()
+        return [e0.elapsed_time(e1) for e0, e1 in evs]
+
+
+# ---------------------------------------------------------------------------
+def section_plain(args, torch, mg, synth, stream, line):
     dev = torch.device("cuda:0")
-    mg.load()
-
-    # inputs, resident in HBM
     data = []
     for (m, n, k) in SHAPES:
         A, B = synth.pair(m, n, k, seed=0)
-        dA = torch.from_numpy(A).to(dev)
-        dB = torch.from_numpy(B).to(dev)
-        dC = torch.empty((m, n), dtype=torch.float32, device=dev)
-        data.append((A, B, dA, dB, dC))
-    stream = torch.cuda.current_stream()
+        data.append((A, B, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev),
+                     torch.empty((m, n), dtype=torch.float32, device=dev)))
 
     def step(events=None):
         for i, (_, _, dA, dB, dC) in enumerate(data):
@@ -101,7 +125,6 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-
     evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in SHAPES] for _ in range(args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
@@ -118,57 +141,251 @@ def main():
 
     flops_step = sum(2.0 * m * n * k for (m, n, k) in SHAPES)
     value = flops_step * args.steps / (total_ms / 1e3) / 1e12
-    per_shape = []
-    dom = None
+    import oracle
+    per_shape, dom = [], None
+    g = synth.rng(1234)
     for i, (m, n, k) in enumerate(SHAPES):
         ms = [evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(args.steps)]
         avg = float(np.mean(ms))
         tf = 2.0 * m * n * k / (avg / 1e3) / 1e12
         cfg, split = mg.tuner_lookup(mg.MODE_F32, m, n, k)
-        per_shape.append({"m": m, "n": n, "k": k, "ms_avg": round(avg, 4), "ms_min": round(float(np.min(ms)), 4),
-                          "tflops": round(tf, 2), "frac_peak": round(tf / PEAK_FP32_MFMA_TFLOPS, 4),
-                          "cfg": mg.config_info(mg.MODE_F32, cfg), "split_k": split})
-        if (m, n, k) == DOMINANT:
-            dom = (avg, tf)
-
-    # sampled normwise error of every shape against the binary64 oracle
-    import oracle
-    g = synth.rng(1234)
-    for i, (m, n, k) in enumerate(SHAPES):
         A, B, _, _, dC = data[i]
         C = dC.cpu().numpy()
         rows = g.integers(0, m, size=args.samples)
         cols = g.integers(0, n, size=args.samples)
         R = oracle.gemm_sampled(A, B, rows, cols)
-        per_shape[i]["rel_err_sampled"] = float(oracle.relerr(C[rows, cols], R))
-
-    achieved = dom[1]
-    line = {
-        "metric": "GEMM TFLOP/s (fp32, plain) and % MFMA peak at stated error",
+        per_shape.append({"m": m, "n": n, "k": k, "ms_avg": round(avg, 4), "ms_min": round(float(np.min(ms)), 4),
+                          "tflops": round(tf, 2), "frac_peak": round(tf / PEAK["f32"], 4),
+                          "cfg": mg.config_info(mg.MODE_F32, cfg), "split_k": split,
+                          "rel_err_sampled": float(oracle.relerr(C[rows, cols], R))})
+        if (m, n, k) == DOMINANT:
+            dom = (avg, tf)
+    line.update({
         "value": round(value, 3),
-        "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": round(total_ms / args.steps, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
+        "roofline": {"bound": "mfma", "achieved": round(dom[1], 3), "peak": PEAK["f32"], "unit": "TFLOP/s",
+                     "frac": round(dom[1] / PEAK["f32"], 4), "traffic": None,
+                     "kernel": "gemm_plain_kernel<F32Cfg<256,256>>, 8192^3", "avg_launch_ms": round(dom[0], 4)},
+        "per_shape": per_shape,
+        "max_rel_err_sampled": max(p["rel_err_sampled"] for p in per_shape),
+        "wall_s_timed": round(wall, 3),
+    })
+    if not args.no_cpu_baseline:
+        A, B = data[SHAPES.index(DOMINANT)][:2]
+        line["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
+    del data
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+def section_precision(args, torch, mg, synth, stream, line):
+    import oracle
+    from oracle import formats as F
+    T = Timer(torch, stream)
+    m = n = k = 8192
+    out = []
+    for dist in ("normal", "wide"):
+        A, B = synth.pair(m, n, k, seed=0, dist=dist)
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        C = torch.empty((m, n), device="cuda")
+        g = synth.rng(77)
+        rows = g.integers(0, m, size=args.samples)
+        cols = g.integers(0, n, size=args.samples)
+        Ar, Bc = A[rows], np.ascontiguousarray(B[:, cols])
+        idx = np.arange(args.samples)
+        R64 = oracle.gemm_sampled(Ar, Bc, idx, idx)
+        for mode in (mg.MODE_BF16, mg.MODE_F16, mg.MODE_F8E4M3, mg.MODE_SPLIT_BF16X3):
+            name = mg.MODE_NAMES[mode]
+            t_prep = None
+            if mode in (mg.MODE_BF16, mg.MODE_F16):
+                prep = lambda: (mg.convert(dA, mode, stream=stream), mg.convert(dB, mode, stream=stream))
+                t_prep = float(np.median(T.time(prep, 3)))
+                a, b = prep()
+                sa = sb = 1.0
+            elif mode == mg.MODE_F8E4M3:
+                def prep():
+                    qa, s1 = mg.quantize_e4m3(dA, stream=stream)
+                    qb, s2 = mg.quantize_e4m3(dB, stream=stream)
+                    return qa, qb, s1, s2
+                t_prep = float(np.median(T.time(prep, 3)))
+                a, b, s1, s2 = prep()
+                torch.cuda.synchronize()
+                sa, sb = float(s1.cpu()[0]), float(s2.cpu()[0])
+            else:
+                a, b, sa, sb = dA, dB, 1.0, 1.0
+            ms = T.time(lambda: mg.gemm(a, b, out=C, mode=mode, scale_a=sa, scale_b=sb, stream=stream), 5)
+            avg = float(np.mean(ms))
+            tf = 2.0 * m * n * k / (avg / 1e3) / 1e12
+            got = C.cpu().numpy()[rows, cols]
+            rec = {"mode": name, "dist": dist, "ms_avg": round(avg, 4), "tflops": round(tf, 2),
+                   "rel_err_vs_fp64": float(oracle.relerr(got, R64))}
+            if mode == mg.MODE_SPLIT_BF16X3:
+                rec["fp32_equiv_frac_of_fp32_peak"] = round(tf / PEAK["f32"], 4)
+                rec["mfma_bf16_util"] = round(3 * tf / PEAK["bf16"], 4)
+            else:
+                rec["frac_peak"] = round(tf / PEAK[name], 4)
+                rec["prep_ms"] = round(t_prep, 4)
+            cfg, split = mg.tuner_lookup(mode, m, n, k)
+            rec["cfg"] = mg.config_info(mode, cfg)
+            out.append(rec)
+            log(f"precision {rec}")
+            del a, b
+        del dA, dB, C
+        torch.cuda.empty_cache()
+    line["precision_8192"] = out
+
+
+# ---------------------------------------------------------------------------
+def section_grouped(args, torch, mg, synth, stream, line):
+    T = Timer(torch, stream)
+    probs = synth.grouped_problems(512, 32, 1024, seed=0)
+    flops = sum(2.0 * A.shape[0] * B.shape[1] * A.shape[1] for A, B in probs)
+    res = []
+    for mode in (mg.MODE_F32, mg.MODE_BF16):
+        ops = []
+        for A, B in probs:
+            a, b = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+            if mode != mg.MODE_F32:
+                a, b = mg.convert(a, mode), mg.convert(b, mode)
+            ops.append((a, b, torch.empty((A.shape[0], B.shape[1]), device="cuda")))
+        torch.cuda.synchronize()
+        graph = mg.GroupedGraph(ops, mode=mode)
+        t_graph = T.time(lambda: graph.launch(stream), 10, warmup=2)
+        t_grouped = T.time(lambda: mg.grouped(ops, mode=mode, stream=stream), 10, warmup=2)
+
+        def plain_all():
+            for a, b, c in ops:
+                mg.gemm(a, b, out=c, mode=mode, stream=stream)
+        t_plain = T.time(plain_all, 5, warmup=1)
+        # the 512 plain launches captured in one graph: launch overhead removed
+        g = None
+        try:
+            g = torch.cuda.CUDAGraph()
+            s2 = torch.cuda.Stream()
+            with torch.cuda.stream(s2):
+                plain_all_s2 = lambda: [mg.gemm(a, b, out=c, mode=mode, stream=s2) for a, b, c in ops]
+                plain_all_s2()
+                torch.cuda.synchronize()
+                with torch.cuda.graph(g, stream=s2):
+                    plain_all_s2()
+            t_plain_graph = T.time(lambda: g.replay(), 5, warmup=1)
+        except Exception as e:  # capture of the plain path is informational only
+            log(f"plain-launch graph capture failed: {e}")
+            t_plain_graph = [float("nan")]
+        rec = {"mode": mg.MODE_NAMES[mode], "gflop": round(flops / 1e9, 3),
+               "graph_ms": round(float(np.median(t_graph)), 4),
+               "grouped_ms": round(float(np.median(t_grouped)), 4),
+               "plain_512_ms": round(float(np.median(t_plain)), 4),
+               "plain_512_graph_ms": (round(float(np.median(t_plain_graph)), 4)
+                                      if np.isfinite(np.median(t_plain_graph)) else None)}
+        rec["graph_tflops"] = round(flops / (rec["graph_ms"] / 1e3) / 1e12, 2)
+        rec["speedup_vs_plain"] = round(rec["plain_512_ms"] / rec["graph_ms"], 2)
+        res.append(rec)
+        log(f"grouped {rec}")
+        graph.close()
+        del ops, g
+        torch.cuda.empty_cache()
+    line["grouped_512"] = res
+
+
+# ---------------------------------------------------------------------------
+def section_serving(args, torch, mg, synth, stream, line):
+    from paper_1306_6192_amd import _lib
+    lib = _lib.load()
+    N = args.serve_requests
+    dims = synth.loguniform_dims(N, 64, 4096, seed=0)
+    mix = synth.dtype_mix(N, seed=1)
+    modes = [(mg.MODE_F32, mg.MODE_BF16, mg.MODE_F8E4M3)[i] for i in mix]
+    # resident operand pools: one float32 pool and its BF16 / E4M3 images
+    pool_elems = 64 << 20
+    g = synth.rng(2)
+    pool32 = torch.from_numpy(synth.draw(g, (pool_elems,), "uniform")).cuda()
+    pool16 = mg.convert(pool32, mg.MODE_BF16)
+    pool8, s8 = mg.quantize_e4m3(pool32)
+    torch.cuda.synchronize()
+    s8 = float(s8.cpu()[0])
+    esz = {mg.MODE_F32: 4, mg.MODE_BF16: 2, mg.MODE_F8E4M3: 1}
+    base = {mg.MODE_F32: pool32.data_ptr(), mg.MODE_BF16: pool16.data_ptr(), mg.MODE_F8E4M3: pool8.data_ptr()}
+    # output arena: consecutive requests take consecutive regions (ring)
+    arena_bytes = 24 << 30
+    arena = torch.empty(arena_bytes // 4, dtype=torch.float32, device="cuda")
+    budget = 8 << 30
+    probs, flops = [], 0.0
+    off_c = 0
+    for i, ((m, n, k), mode) in enumerate(zip(dims, modes)):
+        m, n, k = int(m), int(n), int(k)
+        oa = int(g.integers(0, pool_elems - m * k))
+        ob = int(g.integers(0, pool_elems - k * n))
+        if off_c + m * n * 4 > arena_bytes:
+            off_c = 0
+        sa = sb = s8 if mode == mg.MODE_F8E4M3 else 1.0
+        probs.append(_lib.problem(mode, m, n, k, base[mode] + oa * esz[mode], k, base[mode] + ob * esz[mode], n,
+                                  arena.data_ptr() + off_c, n, sa, sb))
+        off_c += (m * n * 4 + 255) // 256 * 256
+        flops += 2.0 * m * n * k
+    arr = _lib.problems_array(probs)
+    out = {"requests": N, "total_tflop": round(flops / 1e12, 3), "budget_gb": budget / 2**30, "rates": []}
+    for rate in [float(r) for r in args.serve_rates.split(",")]:
+        offs = (synth.poisson_arrivals(N, rate, seed=3) * 1e9).astype(np.uint64)
+        for executor, label in ((0, "batched"), (2, "plain_fifo")):
+            cfg = _lib.ServeConfig(budget, 256, 4, 64, 1 << 20, executor, 0)
+            h = ctypes.c_void_p()
+            _lib.check(lib.gemm_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+            tickets = (ctypes.c_uint64 * N)()
+            _lib.check(lib.gemm_serve_replay(h, arr, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), N,
+                                             tickets))
+            _lib.check(lib.gemm_serve_drain(h))
+            lat, t_first, t_last, bs = [], None, 0, []
+            for i in range(N):
+                r = _lib.ServeResult()
+                _lib.check(lib.gemm_serve_poll(h, tickets[i], ctypes.byref(r)))
+                lat.append((r.t_done_ns - r.t_arrival_ns) / 1e6)
+                t_first = r.t_arrival_ns if t_first is None else min(t_first, r.t_arrival_ns)
+                t_last = max(t_last, r.t_done_ns)
+                bs.append(r.batch_size)
+            st = _lib.ServeStats()
+            lib.gemm_serve_stats(h, ctypes.byref(st))
+            _lib.check(lib.gemm_serve_destroy(h))
+            lat = np.array(lat)
+            rec = {"rate_per_s": rate, "executor": label, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                   "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
+                   "tflops": round(flops / ((t_last - t_first) / 1e9) / 1e12, 2),
+                   "mean_batch": round(float(np.mean(bs)), 2),
+                   "peak_inflight_gb": round(st.peak_inflight_bytes / 2**30, 3)}
+            out["rates"].append(rec)
+            log(f"serving {rec}")
+    line["serving"] = out
+    del arena, pool32, pool16, pool8
+    torch.cuda.empty_cache()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus above 1 is not supported"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1306_6192_amd as mg
+    import synth
+
+    torch.cuda.set_device(0)
+    mg.load()
+    stream = torch.cuda.current_stream()
+    sections = [s for s in args.sections.split(",") if s]
+    line = {
+        "metric": "GEMM TFLOP/s (fp32, plain) and % MFMA peak at stated error; serve p50/p99 latency",
+        "value": None, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic: uniform[-1,1] float32, numpy default_rng seed 0 (A then B)",
         "config": {"workload": "plain fp32 gemm, one product each of (m,n,k) = 2048^3, 4096^3, 8192^3, "
                                "(8192,1024,4096), (128,8192,8192), row-major",
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
-                     "kernel": "gemm_f32_plain_kernel, 8192^3", "avg_launch_ms": round(dom[0], 4)},
-        "per_shape": per_shape,
-        "max_rel_err_sampled": max(p["rel_err_sampled"] for p in per_shape),
-        "wall_s_timed": round(wall, 3),
     }
-    if not args.no_cpu_baseline:
-        A, B = data[SHAPES.index(DOMINANT)][:2]
-        line["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
+    for name in sections:
+        log(f"section {name}")
+        {"plain": section_plain, "precision": section_precision, "grouped": section_grouped,
+         "serving": section_serving}[name](args, torch, mg, synth, stream, line)
     print(json.dumps(line), flush=True)
 
 
