@@ -53,11 +53,32 @@ def parse():
     ap.add_argument("--samples", type=int, default=512, help="sampled outputs per product for the error")
     ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--serve-rates", default="4000,16000,64000")
+    ap.add_argument("--precision-modes", default="bf16,f16,e4m3,split_bf16x3")
+    ap.add_argument("--precision-dists", default="normal,wide")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy (section copy)")
     return ap.parse_args()
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of `key` from the committed counter record
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))[key]
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return rec["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(A, B, target_s: float):
@@ -164,7 +185,8 @@ def section_plain(args, torch, mg, synth, stream, line):
         "value": round(value, 3),
         "ms_per_step": round(total_ms / args.steps, 4),
         "roofline": {"bound": "mfma", "achieved": round(dom[1], 3), "peak": PEAK["f32"], "unit": "TFLOP/s",
-                     "frac": round(dom[1] / PEAK["f32"], 4), "traffic": None,
+                     "frac": round(dom[1] / PEAK["f32"], 4),
+                     "traffic": measured_traffic("gemm_plain_kernel<F32Cfg<256,256>> 8192^3"),
                      "kernel": "gemm_plain_kernel<F32Cfg<256,256>>, 8192^3", "avg_launch_ms": round(dom[0], 4)},
         "per_shape": per_shape,
         "max_rel_err_sampled": max(p["rel_err_sampled"] for p in per_shape),
@@ -184,7 +206,8 @@ def section_precision(args, torch, mg, synth, stream, line):
     T = Timer(torch, stream)
     m = n = k = 8192
     out = []
-    for dist in ("normal", "wide"):
+    want = set(args.precision_modes.split(","))
+    for dist in args.precision_dists.split(","):
         A, B = synth.pair(m, n, k, seed=0, dist=dist)
         dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
         C = torch.empty((m, n), device="cuda")
@@ -196,6 +219,8 @@ def section_precision(args, torch, mg, synth, stream, line):
         R64 = oracle.gemm_sampled(Ar, Bc, idx, idx)
         for mode in (mg.MODE_BF16, mg.MODE_F16, mg.MODE_F8E4M3, mg.MODE_SPLIT_BF16X3):
             name = mg.MODE_NAMES[mode]
+            if name not in want:
+                continue
             t_prep = None
             if mode in (mg.MODE_BF16, mg.MODE_F16):
                 prep = lambda: (mg.convert(dA, mode, stream=stream), mg.convert(dB, mode, stream=stream))
@@ -359,6 +384,19 @@ def section_serving(args, torch, mg, synth, stream, line):
     torch.cuda.empty_cache()
 
 
+def section_copy(args, torch, mg, synth, stream, line):
+    """A plain device copy of known size: the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of the product kernels."""
+    n = args.copy_mib << 18          # float32 elements
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    T = Timer(torch, stream)
+    ms = T.time(lambda: dst.copy_(src), 5, warmup=1)
+    line["copy_calibration"] = {"bytes_read": 4 * n, "bytes_written": 4 * n,
+                                "ms_avg": round(float(np.mean(ms)), 4),
+                                "gb_per_s": round(8.0 * n / (float(np.mean(ms)) / 1e3) / 1e9, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -385,7 +423,7 @@ def main():
     for name in sections:
         log(f"section {name}")
         {"plain": section_plain, "precision": section_precision, "grouped": section_grouped,
-         "serving": section_serving}[name](args, torch, mg, synth, stream, line)
+         "serving": section_serving, "copy": section_copy}[name](args, torch, mg, synth, stream, line)
     print(json.dumps(line), flush=True)
 
 
