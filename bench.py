@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sections", default="plain,precision,grouped,serving")
+    ap.add_argument("--sections", default="plain,precision,grouped,serving,ablation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--samples", type=int, default=512, help="sampled outputs per product for the error")
@@ -384,6 +384,34 @@ def section_serving(args, torch, mg, synth, stream, line):
     torch.cuda.empty_cache()
 
 
+def section_ablation(args, torch, mg, synth, stream, line):
+    """The paper's own comparison at its size (m = n = k = 4096, float):
+    global-memory kernel vs 16x16 shared-memory kernel (Listings 3 and 4,
+    Table 2 / Fig. 8), rebuilt for gfx950, beside the matrix-core kernel."""
+    import oracle
+    T = Timer(torch, stream)
+    m = n = k = 4096
+    A, B = synth.pair(m, n, k, seed=0)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C = torch.empty((m, n), device="cuda")
+    g = synth.rng(91)
+    rows = g.integers(0, m, size=args.samples)
+    cols = g.integers(0, n, size=args.samples)
+    R = oracle.gemm_sampled(A, B, rows, cols)
+    res = []
+    for name, fn in (("paper_global_memory", lambda: mg.paper_kernel(dA, dB, out=C, variant=0, stream=stream)),
+                     ("paper_lds_16x16", lambda: mg.paper_kernel(dA, dB, out=C, variant=1, stream=stream)),
+                     ("mfma_tiled", lambda: mg.gemm(dA, dB, out=C, stream=stream))):
+        ms = T.time(fn, 3, warmup=1)
+        avg = float(np.mean(ms))
+        res.append({"kernel": name, "seconds": round(avg / 1e3, 6),
+                    "tflops": round(2.0 * m * n * k / (avg / 1e3) / 1e12, 3),
+                    "rel_err_sampled": float(oracle.relerr(C.cpu().numpy()[rows, cols], R))})
+        log(f"ablation {res[-1]}")
+    line["ablation_4096"] = {"kernels": res,
+                             "paper_table2_c2050_seconds": {"global_memory": 2.49, "shared_memory": 0.83}}
+
+
 def section_copy(args, torch, mg, synth, stream, line):
     """A plain device copy of known size: the reference for scaling the
     FETCH_SIZE / WRITE_SIZE counters of the product kernels."""
@@ -423,7 +451,7 @@ def main():
     for name in sections:
         log(f"section {name}")
         {"plain": section_plain, "precision": section_precision, "grouped": section_grouped,
-         "serving": section_serving, "copy": section_copy}[name](args, torch, mg, synth, stream, line)
+         "serving": section_serving, "copy": section_copy, "ablation": section_ablation}[name](args, torch, mg, synth, stream, line)
     print(json.dumps(line), flush=True)
 
 

@@ -98,6 +98,14 @@ int gemm_plain(const gemm_problem_t *p, void *stream);
  * gemm_config_info) and split-K factor (>= 1).  For tuning and tests. */
 int gemm_plain_cfg(const gemm_problem_t *p, int32_t cfg, int32_t split_k, void *stream);
 
+/* The paper's own GPU kernels on gfx950, float32 only, as a baseline for the
+ * matrix-core path: variant 0 = one thread per c_ij reading A and B from
+ * global memory (Implementation section, Listing 3); variant 1 = 16x16
+ * blocks staging 16x16 tiles of A and B in LDS (Listing 4).  Bounds-checked
+ * for any shape; same conventions and errors as gemm_plain
+ * (GEMM_EUNSUPPORTED for other modes). */
+int gemm_ablation(const gemm_problem_t *p, int32_t variant, void *stream);
+
 /* Number of tile configurations compiled for `mode`, and their geometry:
  * info[0..5] = {BM, BN, BK, waves, lds_bytes, mfma_k}. */
 int gemm_num_configs(int32_t mode);

@@ -91,6 +91,22 @@ def gemm(A, B, out=None, mode=MODE_F32, scale_a=1.0, scale_b=1.0, cfg=None, spli
     return out
 
 
+def paper_kernel(A, B, out=None, variant=1, stream=None):
+    """C = A @ B (float32) with the paper's kernels rebuilt for gfx950:
+    variant 0 = global-memory thread-per-element, 1 = 16x16 LDS tiles."""
+    torch = _torch()
+    _check_mat(A, "A", MODE_F32)
+    _check_mat(B, "B", MODE_F32)
+    if A.shape[1] != B.shape[0]:
+        raise ValueError("inner dimensions differ")
+    m, n = A.shape[0], B.shape[1]
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float32, device=A.device)
+    p = make_problem(A, B, out, MODE_F32)
+    check(load().gemm_ablation(ctypes.byref(p), int(variant), _stream_ptr(stream)))
+    return out
+
+
 def convert(x, mode, stream=None):
     """float32 -> bfloat16 / float16 codes (RNE), as a tensor of that dtype."""
     torch = _torch()

@@ -13,6 +13,7 @@ from ctypes import (POINTER, Structure, c_char_p, c_float, c_int32, c_int64, c_u
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmi355gemm.so")
+TUNING_TABLE = os.path.join(PKG, "tuning", "mi355x.jsonl")
 
 GEMM_OK = 0
 GEMM_PENDING = 1
@@ -71,6 +72,7 @@ _P = POINTER(GemmProblem)
 _SIGS = {
     "gemm_plain": (c_int32, [_P, c_void_p]),
     "gemm_plain_cfg": (c_int32, [_P, c_int32, c_int32, c_void_p]),
+    "gemm_ablation": (c_int32, [_P, c_int32, c_void_p]),
     "gemm_num_configs": (c_int32, [c_int32]),
     "gemm_config_info": (c_int32, [c_int32, c_int32, POINTER(c_int32)]),
     "gemm_convert_f32": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
@@ -112,6 +114,11 @@ def load():
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
+        # the measured tuning table shipped with the package (MI355X), unless
+        # the environment names another one
+        table = os.environ.get("MI355GEMM_TUNE_FILE") or TUNING_TABLE
+        if os.path.exists(table):
+            lib.gemm_tuner_load(table.encode())
         _lib = lib
     return _lib
 

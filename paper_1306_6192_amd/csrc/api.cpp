@@ -103,6 +103,15 @@ const KernelCfg *configs(int mode, int *count) {
     return lp_configs(mode, count);
 }
 
+int split_grain(int mode) {
+    switch (mode) {
+        case GEMM_MODE_BF16:
+        case GEMM_MODE_F16: return 64;
+        case GEMM_MODE_F8E4M3: return 128;
+        default: return 32;
+    }
+}
+
 static bool vec_ok(const void *ptr, int64_t ld, size_t es) {
     return ((uintptr_t)ptr % 16 == 0) && ((ld * (int64_t)es) % 16 == 0);
 }
@@ -123,13 +132,17 @@ Launch make_launch(const gemm_problem_t &p, const KernelCfg &kc, int split) {
     P.k = (int32_t)p.k;
     P.tiles_m = (int32_t)((p.m + kc.bm - 1) / kc.bm);
     P.tiles_n = (int32_t)((p.n + kc.bn - 1) / kc.bn);
-    const int nkt = (int)((p.k + kc.bk - 1) / kc.bk);
-    split = std::max(1, std::min(split, std::max(1, nkt)));
-    int per = (nkt + split - 1) / split;
+    // Split-K boundaries are placed on multiples of the mode's largest k-tile
+    // (`grain`), so every configuration of a mode splits k at the same places
+    // and sums each element in the same order.
+    const int grain = split_grain(p.mode);
+    const int ngr = (int)((p.k + grain - 1) / grain);
+    split = std::max(1, std::min(split, std::max(1, ngr)));
+    int per = (ngr + split - 1) / split;
     if (per < 1) per = 1;
-    split = std::max(1, (nkt + per - 1) / per);
+    split = std::max(1, (ngr + per - 1) / per);
     P.splits = split;
-    P.kt_per_split = per;
+    P.kt_per_split = per * (grain / kc.bk);
     P.vec = (vec_ok(p.A, p.lda, es) ? 1 : 0) | (vec_ok(p.B, p.ldb, es) ? 2 : 0) |
             (vec_ok(p.C, p.ldc, 4) ? 4 : 0);
     P.scale = p.mode == GEMM_MODE_F8E4M3 ? p.scale_a * p.scale_b : 1.f;
@@ -140,11 +153,27 @@ Launch make_launch(const gemm_problem_t &p, const KernelCfg &kc, int split) {
     return L;
 }
 
+bool cfg_eligible(const gemm_problem_t &p, const KernelCfg &kc) {
+    if (kc.chunk == 0) return true;
+    const int64_t c = kc.chunk;
+    return p.k % c == 0 && p.n % c == 0 && p.n >= c && p.lda % c == 0 && p.ldb % c == 0 &&
+           (uintptr_t)p.A % 16 == 0 && (uintptr_t)p.B % 16 == 0;
+}
+
+int effective_cfg(const gemm_problem_t &p, int cfg) {
+    int count = 0;
+    const KernelCfg *t = configs(p.mode, &count);
+    if (!t || cfg < 0 || cfg >= count || cfg_eligible(p, t[cfg])) return cfg;
+    for (int c = 0; c < count; ++c)
+        if (t[c].chunk == 0 && t[c].bm == t[cfg].bm && t[c].bn == t[cfg].bn) return c;
+    return 0;
+}
+
 int64_t plain_ws_bytes(const gemm_problem_t &p, int cfg, int split) {
     int count = 0;
     const KernelCfg *t = configs(p.mode, &count);
     if (!t || cfg < 0 || cfg >= count || p.m == 0 || p.n == 0 || p.k == 0) return 0;
-    return make_launch(p, t[cfg], split).ws_bytes;
+    return make_launch(p, t[effective_cfg(p, cfg)], split).ws_bytes;
 }
 
 int enqueue_plain(const gemm_problem_t &p, int cfg, int split, void *ws, hipStream_t s) {
@@ -157,6 +186,7 @@ int enqueue_plain(const gemm_problem_t &p, int cfg, int split, void *ws, hipStre
     const KernelCfg *t = configs(p.mode, &count);
     if (!t || count == 0) return fail(GEMM_EUNSUPPORTED, "mode %d has no kernels", p.mode);
     if (cfg < 0 || cfg >= count) return fail(GEMM_EINVAL, "config %d out of range [0,%d)", cfg, count);
+    cfg = effective_cfg(p, cfg);
     Launch L = make_launch(p, t[cfg], split);
     if (L.splits > 1) {
         if (!ws) return fail(GEMM_EINTERNAL, "split-K workspace missing");

@@ -1,13 +1,20 @@
-// F16 product kernels: the plain launch for every tile configuration and
-// the grouped persistent launch (128x128 and 64x64 tiles).
+// F16 product kernels: the plain launch for every tile configuration
+// (register-staged tiles for any shape; asynchronous-copy tiles for shapes
+// whose k, n and row strides are whole 16-byte chunks) and the grouped
+// persistent launch (128x128 and 64x64 tiles).
 #include "kernels_impl.hpp"
 #include "tile_lp.hpp"
+#include "tile_lp2.hpp"
 
 static const KernelCfg kTable[] = {
     make_cfg<LpCfg<GEMM_MODE_F16, 256, 256>, 1>(), make_cfg<LpCfg<GEMM_MODE_F16, 256, 128>, 1>(),
     make_cfg<LpCfg<GEMM_MODE_F16, 128, 256>, 1>(), make_cfg<LpCfg<GEMM_MODE_F16, 128, 128>, 2>(),
     make_cfg<LpCfg<GEMM_MODE_F16, 128, 64>, 2>(),  make_cfg<LpCfg<GEMM_MODE_F16, 64, 128>, 2>(),
     make_cfg<LpCfg<GEMM_MODE_F16, 64, 64>, 4>(),
+    // (no 256x256 asynchronous-copy tile for 16-bit inputs: two fragment sets
+    // plus 256 accumulators exceed the register file and spill)
+    make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 128, 4>, 1, 8>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F16, 128, 256, 4>, 1, 8>(), make_cfg<Lp2Cfg<GEMM_MODE_F16, 128, 128, 4>, 2, 8>(),
 };
 
 const KernelCfg *lp_configs_f16(int *count) {

@@ -1,13 +1,20 @@
-// F8E4M3 product kernels: the plain launch for every tile configuration and
-// the grouped persistent launch (128x128 and 64x64 tiles).
+// F8E4M3 product kernels: the plain launch for every tile configuration
+// (register-staged tiles for any shape; asynchronous-copy tiles for shapes
+// whose k, n and row strides are whole 16-byte chunks) and the grouped
+// persistent launch (128x128 and 64x64 tiles).
 #include "kernels_impl.hpp"
 #include "tile_lp.hpp"
+#include "tile_lp2.hpp"
 
 static const KernelCfg kTable[] = {
     make_cfg<LpCfg<GEMM_MODE_F8E4M3, 256, 256>, 1>(), make_cfg<LpCfg<GEMM_MODE_F8E4M3, 256, 128>, 1>(),
     make_cfg<LpCfg<GEMM_MODE_F8E4M3, 128, 256>, 1>(), make_cfg<LpCfg<GEMM_MODE_F8E4M3, 128, 128>, 2>(),
     make_cfg<LpCfg<GEMM_MODE_F8E4M3, 128, 64>, 2>(),  make_cfg<LpCfg<GEMM_MODE_F8E4M3, 64, 128>, 2>(),
     make_cfg<LpCfg<GEMM_MODE_F8E4M3, 64, 64>, 4>(),
+    // (no 256x256 asynchronous-copy FP8 tile: with two 64-VGPR fragment sets
+    // in flight its register allocation produced wrong sums on the device)
+    make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 256, 128, 4>, 1, 16>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 128, 256, 4>, 1, 16>(), make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 128, 128, 4>, 2, 16>(),
 };
 
 const KernelCfg *lp_configs_f8(int *count) {

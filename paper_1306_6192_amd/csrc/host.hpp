@@ -49,6 +49,14 @@ Launch make_launch(const gemm_problem_t &p, const KernelCfg &kc, int split);
 // `Launch::ws_bytes` when the split is above 1.
 int enqueue_plain(const gemm_problem_t &p, int cfg, int split, void *ws, hipStream_t s);
 
+// Whether the problem's shape, strides and alignment meet the configuration's
+// chunk requirement, and the configuration actually run for it: a chunked
+// configuration the problem does not meet is replaced by the any-shape one of
+// the same tile size (both sum every element in the same order).
+bool cfg_eligible(const gemm_problem_t &p, const KernelCfg &kc);
+int split_grain(int mode);
+int effective_cfg(const gemm_problem_t &p, int cfg);
+
 // Split-K workspace bytes the (cfg, split) choice needs for this problem.
 int64_t plain_ws_bytes(const gemm_problem_t &p, int cfg, int split);
 

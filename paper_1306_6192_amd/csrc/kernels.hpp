@@ -24,6 +24,10 @@ struct KernelCfg {
     int bm, bn, bk, waves, lds_bytes, mfma_k;
     int wg_per_cu;             // resident workgroups per CU (register and LDS limits)
     PlainLaunchFn plain;
+    // 0: any shape.  Otherwise the configuration moves whole 16-byte chunks
+    // (`chunk` elements): k, n, lda and ldb must be multiples of it and A, B
+    // 16-byte aligned.
+    int chunk;
 };
 
 // The grouped kernel of a mode: two tile configurations (indices into the

@@ -200,6 +200,19 @@ int Server::launch_batch(Slot &s, std::vector<Request *> &b) {
         MG_HIP(hipEventRecord(s.done, s.stream));
         return GEMM_OK;
     }
+    if (b.size() == 1) {
+        // A batch of one runs as a plain launch of the tile configuration the
+        // grouped kernel would give it (same tiles, no split: the same bits),
+        // without the descriptor upload.
+        const gemm_problem_t &p = b[0]->p;
+        const GroupedKernel *gk = grouped_kernel(p.mode);
+        if (!gk) return fail(GEMM_EUNSUPPORTED, "mode %d has no grouped kernel", p.mode);
+        const int cfg = gk->cfg_idx[grouped_choose(p.mode, p.m, p.n, p.k)];
+        int rc = enqueue_plain(p, cfg, 1, nullptr, s.stream);
+        if (rc != GEMM_OK) return rc;
+        MG_HIP(hipEventRecord(s.done, s.stream));
+        return GEMM_OK;
+    }
     std::vector<gemm_problem_t> ps;
     ps.reserve(b.size());
     for (Request *r : b) ps.push_back(r->p);
@@ -276,9 +289,11 @@ void Server::loop() {
         for (Slot &s : slots) running |= !s.running.empty();
         if (stop && !busy_locked()) break;
         if (running) {
-            // device work in flight: poll its events at a short interval
+            // device work in flight: poll its events.  The scheduler thread
+            // spins (yielding) rather than sleeping: a timed sleep on Linux
+            // lasts tens of microseconds, more than many requests take.
             lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(10));
+            std::this_thread::yield();
             lk.lock();
         } else if (queue.empty() && admitted.empty()) {
             cv_work.wait(lk, [this] { return stop || !queue.empty(); });

@@ -1,0 +1,356 @@
+// Reduced-precision output tile, asynchronous-copy variant (BF16, F16, FP8).
+//
+// Same arithmetic as tile_lp.hpp (same MFMA instructions, same k order, so
+// the two produce identical bits), different data movement:
+//   * A and B go from HBM straight into LDS with 16-byte direct loads
+//     (global_load_lds_dwordx4): no staging registers and no register
+//     transpose; lane L of one such load lands at LDS base + 16*L.
+//   * A ring of STAGES LDS buffers keeps STAGES-1 k-tiles in flight while one
+//     is consumed; each wave waits (vmcnt) only for its own oldest tile and one
+//     barrier per k-tile publishes it.
+//   * B stays row-major (k x n) in LDS; the MFMA B operand (consecutive k of
+//     one column per lane) is gathered with the transposing LDS reads
+//     ds_read_b64_tr_b16 / ds_read_b64_tr_b8.  Within each group of 16 lanes,
+//     lane j receives element j%4 (b16; j%8 for b8) of the 8-byte chunk
+//     addressed by lane 4r + j/4 (b8: 2r + j/8), for r = 0..3 (b8: 0..7); so
+//     lane 4r + c addressing B[k0+r][n0+4c..] yields B[k0..k0+3][n0+j] in
+//     lane j (b8: lane 2r + c addressing B[k0+r][n0+8c..]).
+//   * Rows are XOR-swizzled at 16-byte granularity so that the fragment reads
+//     of 8 (A) or 4-8 (B) consecutive rows hit distinct LDS banks; the
+//     swizzle is applied on the global side of the direct loads (each lane
+//     picks which logical chunk it fetches), since the LDS side is fixed.
+// Shape requirements (checked on the host; other shapes use tile_lp.hpp):
+// k and n multiples of the 16-byte chunk (8 x 16-bit or 16 x 8-bit), row
+// strides multiples of 16 bytes, 16-byte aligned A and B.  Rows of A beyond m
+// and columns of B beyond n read clamped (valid, finite) data whose results
+// are never stored; k beyond the end reads a zero chunk.
+#pragma once
+
+#include "tile_common.hpp"
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+// A 16-byte chunk of zeros in device memory: the source of k positions past
+// the end of the matrices.
+static __device__ __attribute__((aligned(16))) uint32_t g_zero_chunk[4];
+
+// s_waitcnt vmcnt(N) with the other counters left alone (gfx9 encoding:
+// vmcnt[3:0] and [15:14], expcnt[6:4] = 7, lgkmcnt[11:8] = 15).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int MODE_, int BM_, int BN_, int STAGES_>
+struct Lp2Cfg {
+    static constexpr int MODE = MODE_;
+    static constexpr int BM = BM_, BN = BN_, STAGES = STAGES_;
+    static constexpr int WM = 2, WN = 2;
+    static constexpr int TM = BM / WM, TN = BN / WN;
+    static constexpr int RB = TM / 32, CB = TN / 32;
+    static constexpr int ESZ = (MODE == GEMM_MODE_F8E4M3) ? 1 : 2;
+    static constexpr int CE = 16 / ESZ;                 // elements per 16-byte chunk
+    static constexpr int BK = 64 / ESZ;                 // k per k-tile: 64-byte A rows
+    static constexpr int KCH = (MODE == GEMM_MODE_F8E4M3) ? 64 : 16;   // k per MFMA
+    static constexpr int MFMA_K = KCH;
+    static constexpr int STEPS = BK / KCH;
+    static constexpr int A_ROWB = 64;
+    static constexpr int B_ROWB = BN * ESZ;
+    static constexpr int B_CPR = B_ROWB / 16;           // 16-byte chunks per B row
+    static constexpr int A_STAGE = BM * A_ROWB;
+    static constexpr int B_STAGE = BK * B_ROWB;
+    static constexpr int STAGE = A_STAGE + B_STAGE;
+    static constexpr int LDS_BYTES = STAGES * STAGE;
+    static constexpr int A_LOADS = A_STAGE / 1024 / 4;  // direct loads per wave per k-tile
+    static constexpr int B_LOADS = B_STAGE / 1024 / 4;
+    static constexpr int LOADS = A_LOADS + B_LOADS;
+    static_assert(RB >= 1 && CB >= 1, "wave tile");
+    static_assert(A_LOADS >= 1 && B_LOADS >= 1 && A_LOADS * 4096 == A_STAGE && B_LOADS * 4096 == B_STAGE,
+                  "stage sizes must be whole numbers of 4 x 1 KiB loads");
+    static_assert(STAGES >= 2 && (STAGES - 1) * LOADS < 64, "vmcnt range");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+    // physical chunk of logical chunk c in A row r / B row k
+    __device__ static __forceinline__ int a_swz(int r) { return (r >> 1) & 3; }
+    __device__ static __forceinline__ int b_swz(int k) {
+        return (ESZ == 2 ? 4 * (k & 3) : 2 * (k & 7)) & (B_CPR - 1);
+    }
+    __device__ static void run(const TileProblem &P, int tm, int tn, int split, uint8_t *lds);
+};
+
+// One 16-byte direct load per lane into LDS at `lds` + 16 * lane.  Written as
+// inline assembly (M0 = LDS address) so that the compiler does not treat the
+// transfer as an LDS write it must wait for before every later LDS read: the
+// pipeline waits for it explicitly (wait_vmcnt before the k-tile's barrier).
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void load_lds16(const void *src, uint8_t *lds) {
+    uint32_t dst = (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t *)lds);
+    dst = __builtin_amdgcn_readfirstlane(dst);
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(dst), "v"(src) : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// Issue this wave's direct loads of one k-tile (A rows m0.., B rows k0..)
+// into `stage`.
+template <class Cfg>
+__device__ __forceinline__ void lp2_issue(const TileProblem &P, int m0, int n0, int k0, uint8_t *stage) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint8_t *A = static_cast<const uint8_t *>(P.A);
+    const uint8_t *B = static_cast<const uint8_t *>(P.B);
+    const void *zero = g_zero_chunk;
+#pragma unroll
+    for (int j = 0; j < Cfg::A_LOADS; ++j) {
+        const int t = wave * Cfg::A_LOADS + j;          // 1 KiB piece of the A stage
+        const int r = 16 * t + (lane >> 2);             // tile row
+        const int p = lane & 3;                         // physical chunk
+        const int c = p ^ Cfg::a_swz(r);                // logical chunk it holds
+        const int row = min(m0 + r, P.m - 1);
+        const int k = k0 + c * Cfg::CE;
+        const void *src = (k < P.k) ? (const void *)(A + ((int64_t)row * P.lda + k) * Cfg::ESZ) : zero;
+        load_lds16(src, stage + 1024 * t);
+    }
+    uint8_t *Bs = stage + Cfg::A_STAGE;
+#pragma unroll
+    for (int j = 0; j < Cfg::B_LOADS; ++j) {
+        const int t = wave * Cfg::B_LOADS + j;
+        const int slot = 64 * t + lane;
+        const int kr = slot / Cfg::B_CPR;
+        const int p = slot % Cfg::B_CPR;
+        const int c = p ^ Cfg::b_swz(kr);
+        const int k = k0 + kr;
+        const int n = min(n0 + c * Cfg::CE, P.n - Cfg::CE);
+        const void *src = (k < P.k) ? (const void *)(B + ((int64_t)k * P.ldb + n) * Cfg::ESZ) : zero;
+        load_lds16(src, Bs + 1024 * t);
+    }
+}
+
+// MFMA operand fragments of one k-step (KCH consecutive k) for the wave's
+// RB x CB accumulator blocks.
+template <class Cfg, bool FP8 = (Cfg::MODE == GEMM_MODE_F8E4M3)>
+struct Lp2Frag;
+template <class Cfg>
+struct Lp2Frag<Cfg, false> {
+    u32x4 a[Cfg::RB];
+    u32x4 b[Cfg::CB];
+};
+template <class Cfg>
+struct Lp2Frag<Cfg, true> {
+    i32x8 a[Cfg::RB];
+    i32x8 b[Cfg::CB];
+};
+
+// Read the fragments of k-step kc of the k-tile held in `stage`.
+template <class Cfg>
+__device__ __forceinline__ void lp2_read(const uint8_t *stage, int kc, Lp2Frag<Cfg> &F) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
+    const int l32 = lane & 31, g = lane >> 5;
+    const int p16 = lane & 15, G = lane >> 4;
+    const uint8_t *As = stage;
+    const uint8_t *Bs = stage + Cfg::A_STAGE;
+    if constexpr (Cfg::MODE == GEMM_MODE_F8E4M3) {
+#pragma unroll
+        for (int rb = 0; rb < Cfg::RB; ++rb) {
+            const int r = wm * Cfg::TM + rb * 32 + l32;
+            const uint8_t *row = As + r * Cfg::A_ROWB;
+            const u32x4 lo = *reinterpret_cast<const u32x4 *>(row + 16 * ((2 * g) ^ Cfg::a_swz(r)));
+            const u32x4 hi = *reinterpret_cast<const u32x4 *>(row + 16 * ((2 * g + 1) ^ Cfg::a_swz(r)));
+            F.a[rb] = (i32x8){(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
+                              (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+        }
+#pragma unroll
+        for (int cb = 0; cb < Cfg::CB; ++cb) {
+            const int n = wn * Cfg::TN + cb * 32 + 16 * (G & 1) + 8 * (p16 & 1);
+            i32x2 q[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int k = 32 * (G >> 1) + 8 * h + (p16 >> 1);
+                const uint8_t *a = Bs + k * Cfg::B_ROWB + 16 * ((n >> 4) ^ Cfg::b_swz(k)) + (n & 15);
+                q[h] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) i32x2 *)a);
+            }
+            F.b[cb] = (i32x8){q[0][0], q[0][1], q[1][0], q[1][1], q[2][0], q[2][1], q[3][0], q[3][1]};
+        }
+    } else {
+#pragma unroll
+        for (int rb = 0; rb < Cfg::RB; ++rb) {
+            const int r = wm * Cfg::TM + rb * 32 + l32;
+            F.a[rb] = *reinterpret_cast<const u32x4 *>(As + r * Cfg::A_ROWB + 16 * ((2 * kc + g) ^ Cfg::a_swz(r)));
+        }
+#pragma unroll
+        for (int cb = 0; cb < Cfg::CB; ++cb) {
+            const int n = wn * Cfg::TN + cb * 32 + 16 * (G & 1) + 4 * (p16 & 3);
+            s16x4 hv[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = 16 * kc + 8 * (G >> 1) + 4 * h + (p16 >> 2);
+                const uint8_t *a = Bs + k * Cfg::B_ROWB + 16 * ((n >> 3) ^ Cfg::b_swz(k)) + 2 * (n & 7);
+                hv[h] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4 *)a);
+            }
+            const i32x2 lo = __builtin_bit_cast(i32x2, hv[0]);
+            const i32x2 hi = __builtin_bit_cast(i32x2, hv[1]);
+            F.b[cb] = (u32x4){(uint32_t)lo[0], (uint32_t)lo[1], (uint32_t)hi[0], (uint32_t)hi[1]};
+        }
+    }
+}
+
+// MFMAs of accumulator rows [RB0, RB1) for one k-step.
+template <class Cfg, int RB0, int RB1>
+__device__ __forceinline__ void lp2_mfma(const Lp2Frag<Cfg> &F, f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+#pragma unroll
+    for (int rb = RB0; rb < RB1; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < Cfg::CB; ++cb) {
+            if constexpr (Cfg::MODE == GEMM_MODE_F8E4M3)
+                acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(F.a[rb], F.b[cb], acc[rb][cb], 0, 0,
+                                                                             0, 0, 0, 0);
+            else if constexpr (Cfg::MODE == GEMM_MODE_BF16)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, F.a[rb]), __builtin_bit_cast(bf16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
+            else
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                    __builtin_bit_cast(f16x8, F.a[rb]), __builtin_bit_cast(f16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
+        }
+}
+
+// Wait until at most `ahead` later k-tiles' loads of this wave are pending.
+template <class Cfg>
+__device__ __forceinline__ void lp2_wait(int ahead) {
+    static_assert(Cfg::STAGES <= 4, "extend the wait ladder");
+    if constexpr (Cfg::STAGES >= 4) {
+        if (ahead >= 3) {
+            wait_vmcnt<3 * Cfg::LOADS>();
+            return;
+        }
+        if (ahead == 2) {
+            wait_vmcnt<2 * Cfg::LOADS>();
+            return;
+        }
+    }
+    if constexpr (Cfg::STAGES >= 3) {
+        if (ahead == 1 || (Cfg::STAGES == 3 && ahead >= 1)) {
+            if (Cfg::STAGES == 3 && ahead >= 2) wait_vmcnt<2 * Cfg::LOADS>();
+            else wait_vmcnt<Cfg::LOADS>();
+            return;
+        }
+    }
+    if constexpr (Cfg::STAGES == 2) {
+        if (ahead >= 1) {
+            wait_vmcnt<Cfg::LOADS>();
+            return;
+        }
+    }
+    wait_vmcnt<0>();
+}
+
+// Natural-column epilogue: lane l%32 of accumulator block cb holds output
+// column 32*cb + l%32 of the wave's columns.
+template <class Cfg>
+__device__ __forceinline__ void lp2_epilogue(float *__restrict__ C, int64_t ldc, int M, int N, int m0, int n0,
+                                             float scale, const f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
+    const int l32 = lane & 31, g = lane >> 5;
+#pragma unroll
+    for (int rb = 0; rb < Cfg::RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = m0 + wm * Cfg::TM + rb * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+            if (row >= M) continue;
+            float *p = C + (int64_t)row * ldc;
+#pragma unroll
+            for (int cb = 0; cb < Cfg::CB; ++cb) {
+                const int col = n0 + wn * Cfg::TN + cb * 32 + l32;
+                if (col < N) p[col] = acc[rb][cb][r] * scale;
+            }
+        }
+}
+
+// One k-step of the software pipeline: the MFMAs of step s use fragments
+// `cur` (read during step s-1) while the fragments of step s+1 are read into
+// `nxt`.  When step s+1 starts a new k-tile, the first half of step s's MFMAs
+// is issued, then this wave waits for its loads of that k-tile, the
+// workgroup synchronises (which also retires every read of the k-tile just
+// finished, so its LDS stage is refilled with the k-tile STAGES ahead), and
+// the second half of the MFMAs covers the latency of the new reads.
+template <class Cfg>
+__device__ __forceinline__ void lp2_step(const TileProblem &P, int m0, int n0, int kt0, int nt, int s, uint8_t *lds,
+                                         const Lp2Frag<Cfg> &cur, Lp2Frag<Cfg> &nxt,
+                                         f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+    constexpr int H = (Cfg::RB + 1) / 2;
+    const int T = nt * Cfg::STEPS;
+    const int i = s / Cfg::STEPS;
+    if (s + 1 >= T) {
+        lp2_mfma<Cfg, 0, Cfg::RB>(cur, acc);
+        return;
+    }
+    const int kc1 = (s + 1) % Cfg::STEPS;
+    const int i1 = i + (kc1 == 0 ? 1 : 0);
+    if (kc1 == 0) {
+        lp2_mfma<Cfg, 0, H>(cur, acc);
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        lp2_wait<Cfg>(min(Cfg::STAGES - 2, nt - 1 - i1));
+        __syncthreads();
+        if (i + Cfg::STAGES < nt)
+            lp2_issue<Cfg>(P, m0, n0, (kt0 + i + Cfg::STAGES) * Cfg::BK, lds + (i % Cfg::STAGES) * Cfg::STAGE);
+        lp2_read<Cfg>(lds + (i1 % Cfg::STAGES) * Cfg::STAGE, 0, nxt);
+        lp2_mfma<Cfg, H, Cfg::RB>(cur, acc);
+    } else {
+        lp2_read<Cfg>(lds + (i1 % Cfg::STAGES) * Cfg::STAGE, kc1, nxt);
+        lp2_mfma<Cfg, 0, Cfg::RB>(cur, acc);
+    }
+}
+
+template <class Cfg>
+__device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, int split, uint8_t *lds) {
+    const int m0 = tm * Cfg::BM, n0 = tn * Cfg::BN;
+    const int nkt = (P.k + Cfg::BK - 1) / Cfg::BK;
+    const int kt0 = split * P.kt_per_split;
+    const int kt1 = min(kt0 + P.kt_per_split, nkt);
+    const int nt = max(0, kt1 - kt0);
+
+    f32x16 acc[Cfg::RB][Cfg::CB];
+#pragma unroll
+    for (int rb = 0; rb < Cfg::RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < Cfg::CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[rb][cb][r] = 0.f;
+
+    if (nt > 0) {
+        // fill the ring: k-tiles 0 .. STAGES-1
+#pragma unroll
+        for (int s = 0; s < Cfg::STAGES; ++s)
+            if (s < nt) lp2_issue<Cfg>(P, m0, n0, (kt0 + s) * Cfg::BK, lds + s * Cfg::STAGE);
+        // k-tile 0 ready: at most STAGES-1 later k-tiles still pending
+        const int ahead0 = min(Cfg::STAGES - 1, nt - 1);
+        if (ahead0 >= Cfg::STAGES - 1) wait_vmcnt<(Cfg::STAGES - 1) * Cfg::LOADS>();
+        else lp2_wait<Cfg>(ahead0);
+        __syncthreads();
+        Lp2Frag<Cfg> f0, f1;
+        lp2_read<Cfg>(lds, 0, f0);
+        const int T = nt * Cfg::STEPS;
+        for (int s = 0; s < T; s += 2) {
+            lp2_step<Cfg>(P, m0, n0, kt0, nt, s, lds, f0, f1, acc);
+            if (s + 1 < T) lp2_step<Cfg>(P, m0, n0, kt0, nt, s + 1, lds, f1, f0, acc);
+        }
+    }
+    __syncthreads();   // the LDS ring may be refilled by this workgroup's next tile
+    float *C;
+    int64_t ldc;
+    float scale;
+    epilogue_target(P, split, C, ldc, scale);
+    lp2_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
+}
+
+template <int MODE, int BM, int BN, int STAGES>
+__device__ __forceinline__ void Lp2Cfg<MODE, BM, BN, STAGES>::run(const TileProblem &P, int tm, int tn, int split,
+                                                                   uint8_t *lds) {
+    lp2_tile<Lp2Cfg<MODE, BM, BN, STAGES>>(P, tm, tn, split, lds);
+}

@@ -45,8 +45,14 @@ void heuristic_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg_out, i
     double best = 1e300;
     for (int c = 0; c < count; ++c) {
         const KernelCfg &kc = t[c];
+        // chunked (asynchronous-copy) tiles need k and n in whole 16-byte
+        // chunks; for FP8, whose register-staged tile spends most of its time
+        // waiting for loads, they are the faster choice (measured), for
+        // 16-bit inputs the measured table decides
+        if (kc.chunk && (k % kc.chunk || n % kc.chunk)) continue;
+        const double bonus = (kc.chunk && mode == GEMM_MODE_F8E4M3) ? 2.0 : 1.0;
         const int64_t tiles = ((m + kc.bm - 1) / kc.bm) * ((n + kc.bn - 1) / kc.bn);
-        const int64_t nkt = (k + kc.bk - 1) / kc.bk;
+        const int64_t nkt = (k + split_grain(mode) - 1) / split_grain(mode) * (split_grain(mode) / kc.bk);
         for (int split = 1; split <= 16; split *= 2) {
             if (split > 1 && nkt / split < 4) break;
             const int64_t per = (nkt + split - 1) / split;
@@ -55,7 +61,7 @@ void heuristic_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg_out, i
             const double rounds = std::ceil((double)wgs / slots);
             // time ~ rounds * (work of one CU slot-set) / efficiency
             const double per_round = (double)std::max(1, kc.wg_per_cu) * kc.bm * kc.bn * (double)(per * kc.bk);
-            double cost = rounds * per_round / tile_eff(kc);
+            double cost = rounds * per_round / (tile_eff(kc) * bonus);
             // split-K pays for writing and re-reading the partial slabs
             if (split > 1) cost += (double)(split + 1) * (double)m * n * 64.0 / cus;
             // a launch that cannot reach every CU also leaves HBM bandwidth idle
@@ -212,7 +218,8 @@ int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream) {
         p.B = B;
         p.C = static_cast<float *>(C);
         for (int c = 0; c < count && rc == GEMM_OK; ++c) {
-            const int64_t nkt = (k + t[c].bk - 1) / t[c].bk;
+            if (!cfg_eligible(p, t[c])) continue;
+            const int64_t nkt = (k + split_grain(mode) - 1) / split_grain(mode);
             int last_split = 0;
             for (int sp = 1; sp <= 16 && rc == GEMM_OK; sp *= 2) {
                 if (sp > 1 && nkt / sp < 4) break;

@@ -112,7 +112,9 @@ def fp8_group_term_pairs(ar, bc):
 
 
 SHAPES = [(1, 1, 1), (7, 5, 3), (33, 31, 65), (64, 64, 64), (127, 129, 255), (129, 257, 100),
-          (255, 3, 513), (3, 255, 1000), (300, 200, 1), (97, 61, 4099)]
+          (255, 3, 513), (3, 255, 1000), (300, 200, 1), (97, 61, 4099),
+          # k and n whole 16-byte chunks: the asynchronous-copy tiles run these
+          (33, 16, 16), (129, 80, 96), (300, 208, 1040), (257, 272, 4112), (1, 48, 4096)]
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -155,12 +157,17 @@ def test_integer_inputs_bit_exact(mode, R_int):
 
 @pytest.mark.parametrize("mode", MODES)
 def test_cross_config_bitwise_and_identity(mode):
+    """Every tile configuration -- register-staged or asynchronous-copy --
+    sums each element in the same order, for each split-K factor."""
     log(f"precision {mg.MODE_NAMES[mode]} cross-config/identity")
-    A, B = synth.pair(190, 170, 333, seed=32, dist="normal")
-    a, b, sa, sb = device_operands(A, B, mode)
-    ref = host(mg.gemm(a, b, mode=mode, scale_a=sa, scale_b=sb, cfg=0, split_k=1))
-    for cfg in range(mg.num_configs(mode)):
-        assert np.array_equal(ref, host(mg.gemm(a, b, mode=mode, scale_a=sa, scale_b=sb, cfg=cfg, split_k=1)))
+    for (m, n, k) in ((190, 170, 333), (190, 176, 2080)):
+        A, B = synth.pair(m, n, k, seed=32, dist="normal")
+        a, b, sa, sb = device_operands(A, B, mode)
+        for split in (1, 3):
+            ref = host(mg.gemm(a, b, mode=mode, scale_a=sa, scale_b=sb, cfg=0, split_k=split))
+            for cfg in range(mg.num_configs(mode)):
+                got = host(mg.gemm(a, b, mode=mode, scale_a=sa, scale_b=sb, cfg=cfg, split_k=split))
+                assert np.array_equal(ref, got), (m, n, k, split, cfg)
     # identity: entries representable in the format come back unchanged
     X = synth.draw(synth.rng(33), (150, 70), "wide_int")   # powers of two, |x| in [2^-8, 2^8]
     if mode == mg.MODE_F8E4M3:

@@ -13,8 +13,8 @@ FAKE_BASE = 0x100000000
 
 def fake_problem(i, m, n, k, mode=0):
     """A problem with distinct fake device addresses (never dereferenced)."""
-    base = FAKE_BASE + i * (1 << 32)
-    return _lib.problem(mode, m, n, k, base, k, base + (1 << 30), n, base + (2 << 30), n)
+    base = FAKE_BASE + i * (1 << 40)
+    return _lib.problem(mode, m, n, k, base, k, base + (1 << 37), n, base + (2 << 37), n)
 
 
 def make_server(**kw):
@@ -95,13 +95,15 @@ def test_admission_budget_fifo_and_completion():
 
 def test_over_budget_and_queue_full():
     lib = _lib.load()
-    p_small = fake_problem(0, 8, 8, 8)
-    p_big = fake_problem(1, 4096, 4096, 4096)
+    # 8192^3 keeps the fake executor busy for ~1.1 ms per request (1 us per
+    # GFLOP), far longer than 50 submissions take
+    p_small = fake_problem(0, 8192, 8192, 8192)
+    p_big = fake_problem(1, 65536, 65536, 65536)
     h = make_server(hbm_budget_bytes=footprint(p_small) * 10, queue_capacity=3, max_inflight=1, num_streams=1,
                     max_batch=1)
     rc, _ = submit(h, p_big)
     assert rc == _lib.GEMM_ENOMEM and "budget" in _lib.last_error()
-    # a queue of capacity 3 behind one in-flight slot fills up quickly
+    # a queue of capacity 3 behind one in-flight slot fills up
     codes = [submit(h, p_small)[0] for _ in range(50)]
     assert _lib.GEMM_EBUSY in codes
     assert lib.gemm_serve_drain(h) == 0
