@@ -218,36 +218,6 @@ __device__ __forceinline__ void lp2_mfma(const Lp2Frag<Cfg> &F, f32x16 (&acc)[Cf
         }
 }
 
-// Wait until at most `ahead` later k-tiles' loads of this wave are pending.
-template <class Cfg>
-__device__ __forceinline__ void lp2_wait(int ahead) {
-    static_assert(Cfg::STAGES <= 4, "extend the wait ladder");
-    if constexpr (Cfg::STAGES >= 4) {
-        if (ahead >= 3) {
-            wait_vmcnt<3 * Cfg::LOADS>();
-            return;
-        }
-        if (ahead == 2) {
-            wait_vmcnt<2 * Cfg::LOADS>();
-            return;
-        }
-    }
-    if constexpr (Cfg::STAGES >= 3) {
-        if (ahead == 1 || (Cfg::STAGES == 3 && ahead >= 1)) {
-            if (Cfg::STAGES == 3 && ahead >= 2) wait_vmcnt<2 * Cfg::LOADS>();
-            else wait_vmcnt<Cfg::LOADS>();
-            return;
-        }
-    }
-    if constexpr (Cfg::STAGES == 2) {
-        if (ahead >= 1) {
-            wait_vmcnt<Cfg::LOADS>();
-            return;
-        }
-    }
-    wait_vmcnt<0>();
-}
-
 // Natural-column epilogue: lane l%32 of accumulator block cb holds output
 // column 32*cb + l%32 of the wave's columns.
 template <class Cfg>
@@ -272,43 +242,41 @@ __device__ __forceinline__ void lp2_epilogue(float *__restrict__ C, int64_t ldc,
         }
 }
 
-// One k-step of the software pipeline: the MFMAs of step s use fragments
-// `cur` (read during step s-1) while the fragments of step s+1 are read into
-// `nxt`.  When step s+1 starts a new k-tile, the first half of step s's MFMAs
-// is issued, then this wave waits for its loads of that k-tile, the
-// workgroup synchronises (which also retires every read of the k-tile just
-// finished, so its LDS stage is refilled with the k-tile STAGES ahead), and
-// the second half of the MFMAs covers the latency of the new reads.
-template <class Cfg>
-__device__ __forceinline__ void lp2_step(const TileProblem &P, int m0, int n0, int kt0, int nt, int s, uint8_t *lds,
+// One k-step of the software pipeline, in one of two fixed forms so that the
+// loop body has no data-dependent branches:
+//   * inner step (the next step reads the same k-tile): read the next
+//     fragments, then issue this step's MFMAs;
+//   * boundary step (the next step starts a new k-tile): issue half of the
+//     MFMAs, retire this wave's LDS reads, wait for this wave's loads of the
+//     next k-tile, synchronise the workgroup (which publishes that k-tile and
+//     frees the stage just consumed), refill the freed stage with the k-tile
+//     STAGES ahead, read the next fragments and issue the other half.
+// Loads are issued for k-tiles past the end too (their sources are the zero
+// chunk), which keeps the number of loads in flight, and so every wait, the
+// same in every iteration.
+template <class Cfg, bool BOUNDARY>
+__device__ __forceinline__ void lp2_step(const TileProblem &P, int m0, int n0, int kt0, int s, uint8_t *lds,
                                          const Lp2Frag<Cfg> &cur, Lp2Frag<Cfg> &nxt,
                                          f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
     constexpr int H = (Cfg::RB + 1) / 2;
-    const int T = nt * Cfg::STEPS;
     const int i = s / Cfg::STEPS;
-    if (s + 1 >= T) {
-        lp2_mfma<Cfg, 0, Cfg::RB>(cur, acc);
-        return;
-    }
-    const int kc1 = (s + 1) % Cfg::STEPS;
-    const int i1 = i + (kc1 == 0 ? 1 : 0);
-    if (kc1 == 0) {
+    if constexpr (BOUNDARY) {
         lp2_mfma<Cfg, 0, H>(cur, acc);
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        lp2_wait<Cfg>(min(Cfg::STAGES - 2, nt - 1 - i1));
+        wait_vmcnt<(Cfg::STAGES - 2) * Cfg::LOADS>();
         __syncthreads();
-        if (i + Cfg::STAGES < nt)
-            lp2_issue<Cfg>(P, m0, n0, (kt0 + i + Cfg::STAGES) * Cfg::BK, lds + (i % Cfg::STAGES) * Cfg::STAGE);
-        lp2_read<Cfg>(lds + (i1 % Cfg::STAGES) * Cfg::STAGE, 0, nxt);
+        lp2_issue<Cfg>(P, m0, n0, (kt0 + i + Cfg::STAGES) * Cfg::BK, lds + (i % Cfg::STAGES) * Cfg::STAGE);
+        lp2_read<Cfg>(lds + ((i + 1) % Cfg::STAGES) * Cfg::STAGE, 0, nxt);
         lp2_mfma<Cfg, H, Cfg::RB>(cur, acc);
     } else {
-        lp2_read<Cfg>(lds + (i1 % Cfg::STAGES) * Cfg::STAGE, kc1, nxt);
+        lp2_read<Cfg>(lds + (i % Cfg::STAGES) * Cfg::STAGE, (s + 1) % Cfg::STEPS, nxt);
         lp2_mfma<Cfg, 0, Cfg::RB>(cur, acc);
     }
 }
 
 template <class Cfg>
 __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, int split, uint8_t *lds) {
+    static_assert(Cfg::STEPS == 1 || Cfg::STEPS == 2, "pipeline written for 1 or 2 steps per k-tile");
     const int m0 = tm * Cfg::BM, n0 = tn * Cfg::BN;
     const int nkt = (P.k + Cfg::BK - 1) / Cfg::BK;
     const int kt0 = split * P.kt_per_split;
@@ -324,24 +292,34 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
             for (int r = 0; r < 16; ++r) acc[rb][cb][r] = 0.f;
 
     if (nt > 0) {
-        // fill the ring: k-tiles 0 .. STAGES-1
+        // Fill the ring with k-tiles 0 .. STAGES-1 (those past kt1 read the
+        // zero chunk or the next split's data; they are never used).
+        const int kend = kt1 * Cfg::BK;
+        TileProblem Q = P;
+        Q.k = min(P.k, kend);   // this split's k range ends at kend
 #pragma unroll
-        for (int s = 0; s < Cfg::STAGES; ++s)
-            if (s < nt) lp2_issue<Cfg>(P, m0, n0, (kt0 + s) * Cfg::BK, lds + s * Cfg::STAGE);
-        // k-tile 0 ready: at most STAGES-1 later k-tiles still pending
-        const int ahead0 = min(Cfg::STAGES - 1, nt - 1);
-        if (ahead0 >= Cfg::STAGES - 1) wait_vmcnt<(Cfg::STAGES - 1) * Cfg::LOADS>();
-        else lp2_wait<Cfg>(ahead0);
+        for (int s = 0; s < Cfg::STAGES; ++s) lp2_issue<Cfg>(Q, m0, n0, (kt0 + s) * Cfg::BK, lds + s * Cfg::STAGE);
+        wait_vmcnt<(Cfg::STAGES - 1) * Cfg::LOADS>();
         __syncthreads();
         Lp2Frag<Cfg> f0, f1;
         lp2_read<Cfg>(lds, 0, f0);
         const int T = nt * Cfg::STEPS;
-        for (int s = 0; s < T; s += 2) {
-            lp2_step<Cfg>(P, m0, n0, kt0, nt, s, lds, f0, f1, acc);
-            if (s + 1 < T) lp2_step<Cfg>(P, m0, n0, kt0, nt, s + 1, lds, f1, f0, acc);
+        int s = 0;
+        if constexpr (Cfg::STEPS == 2) {
+            for (; s < T; s += 2) {
+                lp2_step<Cfg, false>(Q, m0, n0, kt0, s, lds, f0, f1, acc);
+                lp2_step<Cfg, true>(Q, m0, n0, kt0, s + 1, lds, f1, f0, acc);
+            }
+        } else {
+            for (; s + 1 < T; s += 2) {
+                lp2_step<Cfg, true>(Q, m0, n0, kt0, s, lds, f0, f1, acc);
+                lp2_step<Cfg, true>(Q, m0, n0, kt0, s + 1, lds, f1, f0, acc);
+            }
+            if (s < T) lp2_step<Cfg, true>(Q, m0, n0, kt0, s, lds, f0, f1, acc);
         }
+        wait_vmcnt<0>();   // the loads past the end have landed before the ring is reused
     }
-    __syncthreads();   // the LDS ring may be refilled by this workgroup's next tile
+    __syncthreads();       // the LDS ring may be refilled by this workgroup's next tile
     float *C;
     int64_t ldc;
     float scale;
