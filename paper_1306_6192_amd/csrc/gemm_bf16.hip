@@ -11,8 +11,7 @@ static const KernelCfg kTable[] = {
     make_cfg<LpCfg<GEMM_MODE_BF16, 128, 256>, 1>(), make_cfg<LpCfg<GEMM_MODE_BF16, 128, 128>, 2>(),
     make_cfg<LpCfg<GEMM_MODE_BF16, 128, 64>, 2>(),  make_cfg<LpCfg<GEMM_MODE_BF16, 64, 128>, 2>(),
     make_cfg<LpCfg<GEMM_MODE_BF16, 64, 64>, 4>(),
-    // (no 256x256 asynchronous-copy tile for 16-bit inputs: two fragment sets
-    // plus 256 accumulators exceed the register file and spill)
+    make_cfg<Lp2Cfg<GEMM_MODE_BF16, 256, 256, 4>, 1, 8>(),
     make_cfg<Lp2Cfg<GEMM_MODE_BF16, 256, 128, 4>, 1, 8>(),
     make_cfg<Lp2Cfg<GEMM_MODE_BF16, 128, 256, 4>, 1, 8>(), make_cfg<Lp2Cfg<GEMM_MODE_BF16, 128, 128, 4>, 2, 8>(),
 };

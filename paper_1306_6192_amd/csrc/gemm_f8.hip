@@ -11,8 +11,7 @@ static const KernelCfg kTable[] = {
     make_cfg<LpCfg<GEMM_MODE_F8E4M3, 128, 256>, 1>(), make_cfg<LpCfg<GEMM_MODE_F8E4M3, 128, 128>, 2>(),
     make_cfg<LpCfg<GEMM_MODE_F8E4M3, 128, 64>, 2>(),  make_cfg<LpCfg<GEMM_MODE_F8E4M3, 64, 128>, 2>(),
     make_cfg<LpCfg<GEMM_MODE_F8E4M3, 64, 64>, 4>(),
-    // (no 256x256 asynchronous-copy FP8 tile: with two 64-VGPR fragment sets
-    // in flight its register allocation produced wrong sums on the device)
+    make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 256, 256, 4>, 1, 16>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 256, 128, 4>, 1, 16>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 128, 256, 4>, 1, 16>(), make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 128, 128, 4>, 2, 16>(),
 };

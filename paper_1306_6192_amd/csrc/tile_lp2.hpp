@@ -94,38 +94,63 @@ __device__ __forceinline__ void load_lds16(const void *src, uint8_t *lds) {
 }
 #pragma clang diagnostic pop
 
-// Issue this wave's direct loads of one k-tile (A rows m0.., B rows k0..)
-// into `stage`.
+// Per-lane sources of this wave's direct loads, computed once per output
+// tile: the k-tile starting at k0 then only adds k0 times the k stride.
 template <class Cfg>
-__device__ __forceinline__ void lp2_issue(const TileProblem &P, int m0, int n0, int k0, uint8_t *stage) {
+struct Lp2Src {
+    const uint8_t *a[Cfg::A_LOADS];   // A row start + logical chunk
+    int ak[Cfg::A_LOADS];             // k of that chunk within a k-tile
+    const uint8_t *b[Cfg::B_LOADS];   // B row kr of the k-tile + column chunk
+    int bk[Cfg::B_LOADS];             // kr
+    int64_t bstep;                    // bytes between consecutive B rows
+    int kend;                         // loads at k >= kend read the zero chunk
+};
+
+template <class Cfg>
+__device__ __forceinline__ void lp2_sources(const TileProblem &P, int m0, int n0, int kend, Lp2Src<Cfg> &S) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const uint8_t *A = static_cast<const uint8_t *>(P.A);
     const uint8_t *B = static_cast<const uint8_t *>(P.B);
-    const void *zero = g_zero_chunk;
 #pragma unroll
     for (int j = 0; j < Cfg::A_LOADS; ++j) {
         const int t = wave * Cfg::A_LOADS + j;          // 1 KiB piece of the A stage
         const int r = 16 * t + (lane >> 2);             // tile row
-        const int p = lane & 3;                         // physical chunk
-        const int c = p ^ Cfg::a_swz(r);                // logical chunk it holds
+        const int c = (lane & 3) ^ Cfg::a_swz(r);       // logical chunk held by physical chunk lane&3
         const int row = min(m0 + r, P.m - 1);
-        const int k = k0 + c * Cfg::CE;
-        const void *src = (k < P.k) ? (const void *)(A + ((int64_t)row * P.lda + k) * Cfg::ESZ) : zero;
-        load_lds16(src, stage + 1024 * t);
+        S.ak[j] = c * Cfg::CE;
+        S.a[j] = A + ((int64_t)row * P.lda + S.ak[j]) * Cfg::ESZ;
+    }
+#pragma unroll
+    for (int j = 0; j < Cfg::B_LOADS; ++j) {
+        const int slot = 64 * (wave * Cfg::B_LOADS + j) + lane;
+        const int kr = slot / Cfg::B_CPR;
+        const int c = (slot % Cfg::B_CPR) ^ Cfg::b_swz(kr);
+        const int n = min(n0 + c * Cfg::CE, P.n - Cfg::CE);
+        S.bk[j] = kr;
+        S.b[j] = B + ((int64_t)kr * P.ldb + n) * Cfg::ESZ;
+    }
+    S.bstep = P.ldb * Cfg::ESZ;
+    S.kend = kend;
+}
+
+// Issue this wave's direct loads of the k-tile starting at k0 into `stage`.
+template <class Cfg>
+__device__ __forceinline__ void lp2_issue(const Lp2Src<Cfg> &S, int k0, uint8_t *stage) {
+    const int wave = threadIdx.x >> 6;
+    const void *zero = g_zero_chunk;
+    const int64_t aoff = (int64_t)k0 * Cfg::ESZ;
+    const int64_t boff = (int64_t)k0 * S.bstep;
+#pragma unroll
+    for (int j = 0; j < Cfg::A_LOADS; ++j) {
+        const void *src = (k0 + S.ak[j] < S.kend) ? (const void *)(S.a[j] + aoff) : zero;
+        load_lds16(src, stage + 1024 * (wave * Cfg::A_LOADS + j));
     }
     uint8_t *Bs = stage + Cfg::A_STAGE;
 #pragma unroll
     for (int j = 0; j < Cfg::B_LOADS; ++j) {
-        const int t = wave * Cfg::B_LOADS + j;
-        const int slot = 64 * t + lane;
-        const int kr = slot / Cfg::B_CPR;
-        const int p = slot % Cfg::B_CPR;
-        const int c = p ^ Cfg::b_swz(kr);
-        const int k = k0 + kr;
-        const int n = min(n0 + c * Cfg::CE, P.n - Cfg::CE);
-        const void *src = (k < P.k) ? (const void *)(B + ((int64_t)k * P.ldb + n) * Cfg::ESZ) : zero;
-        load_lds16(src, Bs + 1024 * t);
+        const void *src = (k0 + S.bk[j] < S.kend) ? (const void *)(S.b[j] + boff) : zero;
+        load_lds16(src, Bs + 1024 * (wave * Cfg::B_LOADS + j));
     }
 }
 
@@ -251,32 +276,64 @@ __device__ __forceinline__ void lp2_epilogue(float *__restrict__ C, int64_t ldc,
 //     next k-tile, synchronise the workgroup (which publishes that k-tile and
 //     frees the stage just consumed), refill the freed stage with the k-tile
 //     STAGES ahead, read the next fragments and issue the other half.
+// `i` is the k-tile and `u` = i mod STAGES its stage; the callers unroll over
+// u, so every LDS address is a constant offset from a few base registers.
 // Loads are issued for k-tiles past the end too (their sources are the zero
 // chunk), which keeps the number of loads in flight, and so every wait, the
 // same in every iteration.
 template <class Cfg, bool BOUNDARY>
-__device__ __forceinline__ void lp2_step(const TileProblem &P, int m0, int n0, int kt0, int s, uint8_t *lds,
+__device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, int u, int kc, uint8_t *lds,
                                          const Lp2Frag<Cfg> &cur, Lp2Frag<Cfg> &nxt,
                                          f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
     constexpr int H = (Cfg::RB + 1) / 2;
-    const int i = s / Cfg::STEPS;
     if constexpr (BOUNDARY) {
         lp2_mfma<Cfg, 0, H>(cur, acc);
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         wait_vmcnt<(Cfg::STAGES - 2) * Cfg::LOADS>();
         __syncthreads();
-        lp2_issue<Cfg>(P, m0, n0, (kt0 + i + Cfg::STAGES) * Cfg::BK, lds + (i % Cfg::STAGES) * Cfg::STAGE);
-        lp2_read<Cfg>(lds + ((i + 1) % Cfg::STAGES) * Cfg::STAGE, 0, nxt);
+        lp2_issue<Cfg>(S, (kt0 + i + Cfg::STAGES) * Cfg::BK, lds + u * Cfg::STAGE);
+        lp2_read<Cfg>(lds + ((u + 1) % Cfg::STAGES) * Cfg::STAGE, 0, nxt);
         lp2_mfma<Cfg, H, Cfg::RB>(cur, acc);
     } else {
-        lp2_read<Cfg>(lds + (i % Cfg::STAGES) * Cfg::STAGE, (s + 1) % Cfg::STEPS, nxt);
+        lp2_read<Cfg>(lds + u * Cfg::STAGE, kc + 1, nxt);
         lp2_mfma<Cfg, 0, Cfg::RB>(cur, acc);
+    }
+}
+
+// All steps of k-tile i (stage u).  On entry `fa` holds the tile's step-0
+// fragments; on exit the next tile's step-0 fragments are in `fa` (two steps
+// per k-tile) or in `fb` (one step).
+template <class Cfg>
+__device__ __forceinline__ void lp2_ktile(const Lp2Src<Cfg> &S, int kt0, int i, int u, uint8_t *lds,
+                                          Lp2Frag<Cfg> &fa, Lp2Frag<Cfg> &fb, f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+    if constexpr (Cfg::STEPS == 2) {
+        lp2_step<Cfg, false>(S, kt0, i, u, 0, lds, fa, fb, acc);
+        lp2_step<Cfg, true>(S, kt0, i, u, 1, lds, fb, fa, acc);
+    } else {
+        lp2_step<Cfg, true>(S, kt0, i, u, 0, lds, fa, fb, acc);
+    }
+}
+
+// Two consecutive k-tiles i, i+1 in stages u, u+1 (u even), keeping the
+// fragments in f0 at entry and exit.
+template <class Cfg>
+__device__ __forceinline__ void lp2_pair(const Lp2Src<Cfg> &S, int kt0, int i, int u, int nt, bool guard,
+                                         uint8_t *lds, Lp2Frag<Cfg> &f0, Lp2Frag<Cfg> &f1,
+                                         f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+    if (!guard || i < nt) {
+        if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg>(S, kt0, i, u, lds, f0, f1, acc);
+        else lp2_ktile<Cfg>(S, kt0, i, u, lds, f0, f1, acc);
+    }
+    if (!guard || i + 1 < nt) {
+        if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg>(S, kt0, i + 1, u + 1, lds, f0, f1, acc);
+        else lp2_ktile<Cfg>(S, kt0, i + 1, u + 1, lds, f1, f0, acc);
     }
 }
 
 template <class Cfg>
 __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, int split, uint8_t *lds) {
     static_assert(Cfg::STEPS == 1 || Cfg::STEPS == 2, "pipeline written for 1 or 2 steps per k-tile");
+    static_assert(Cfg::STAGES % 2 == 0, "k-tiles are processed in pairs of stages");
     const int m0 = tm * Cfg::BM, n0 = tn * Cfg::BN;
     const int nkt = (P.k + Cfg::BK - 1) / Cfg::BK;
     const int kt0 = split * P.kt_per_split;
@@ -293,30 +350,23 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
 
     if (nt > 0) {
         // Fill the ring with k-tiles 0 .. STAGES-1 (those past kt1 read the
-        // zero chunk or the next split's data; they are never used).
-        const int kend = kt1 * Cfg::BK;
-        TileProblem Q = P;
-        Q.k = min(P.k, kend);   // this split's k range ends at kend
+        // zero chunk; they are never used).
+        Lp2Src<Cfg> S;
+        lp2_sources<Cfg>(P, m0, n0, min(P.k, kt1 * Cfg::BK), S);
 #pragma unroll
-        for (int s = 0; s < Cfg::STAGES; ++s) lp2_issue<Cfg>(Q, m0, n0, (kt0 + s) * Cfg::BK, lds + s * Cfg::STAGE);
+        for (int s = 0; s < Cfg::STAGES; ++s) lp2_issue<Cfg>(S, (kt0 + s) * Cfg::BK, lds + s * Cfg::STAGE);
         wait_vmcnt<(Cfg::STAGES - 1) * Cfg::LOADS>();
         __syncthreads();
         Lp2Frag<Cfg> f0, f1;
         lp2_read<Cfg>(lds, 0, f0);
-        const int T = nt * Cfg::STEPS;
-        int s = 0;
-        if constexpr (Cfg::STEPS == 2) {
-            for (; s < T; s += 2) {
-                lp2_step<Cfg, false>(Q, m0, n0, kt0, s, lds, f0, f1, acc);
-                lp2_step<Cfg, true>(Q, m0, n0, kt0, s + 1, lds, f1, f0, acc);
-            }
-        } else {
-            for (; s + 1 < T; s += 2) {
-                lp2_step<Cfg, true>(Q, m0, n0, kt0, s, lds, f0, f1, acc);
-                lp2_step<Cfg, true>(Q, m0, n0, kt0, s + 1, lds, f1, f0, acc);
-            }
-            if (s < T) lp2_step<Cfg, true>(Q, m0, n0, kt0, s, lds, f0, f1, acc);
+        int i = 0;
+        for (; i + Cfg::STAGES <= nt; i += Cfg::STAGES) {
+#pragma unroll
+            for (int u = 0; u < Cfg::STAGES; u += 2) lp2_pair<Cfg>(S, kt0, i + u, u, nt, false, lds, f0, f1, acc);
         }
+        // the last nt mod STAGES k-tiles (stages 0 ..)
+#pragma unroll
+        for (int u = 0; u < Cfg::STAGES; u += 2) lp2_pair<Cfg>(S, kt0, i + u, u, nt, true, lds, f0, f1, acc);
         wait_vmcnt<0>();   // the loads past the end have landed before the ring is reused
     }
     __syncthreads();       // the LDS ring may be refilled by this workgroup's next tile
