@@ -93,13 +93,47 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan) {
     return GEMM_OK;
 }
 
-int enqueue_group(const GroupPlan &plan, const GroupDesc *dev_descs, hipStream_t s) {
+int enqueue_group(const GroupPlan &plan, const GroupDesc *dev_descs, int32_t *counters, hipStream_t s) {
     if (plan.total_tiles == 0) return GEMM_OK;
     GroupedArgs G;
     G.descs = dev_descs;
     G.count = (int32_t)plan.descs.size();
     G.total_tiles = plan.total_tiles;
+    G.counters = counters;
     MG_HIP(plan.gk->launch(G, plan.nwg, s));
+    return GEMM_OK;
+}
+
+int alloc_counters(int32_t **out) {
+    *out = nullptr;
+    void *p = nullptr;
+    if (hipMalloc(&p, 256) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GEMM_ENOMEM, "work-queue counters");
+    }
+    if (hipMemset(p, 0, 256) != hipSuccess) {
+        (void)hipFree(p);
+        return fail(GEMM_EHIP, "zeroing work-queue counters failed");
+    }
+    *out = static_cast<int32_t *>(p);
+    return GEMM_OK;
+}
+
+// The work-queue counters of a stream's grouped launches (zeroed once; every
+// launch leaves them at zero).
+static std::mutex g_cnt_mu;
+static std::map<std::pair<int, hipStream_t>, int32_t *> g_cnt;
+
+static int stream_counters(hipStream_t s, int32_t **out) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_cnt_mu);
+    int32_t *&c = g_cnt[{dev, s}];
+    if (!c) {
+        int rc = alloc_counters(&c);
+        if (rc != GEMM_OK) return rc;
+    }
+    *out = c;
     return GEMM_OK;
 }
 
@@ -147,6 +181,7 @@ struct GroupGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void *descs = nullptr;
+    int32_t *counters = nullptr;
 };
 
 }  // namespace mg
@@ -162,9 +197,12 @@ int gemm_grouped(const gemm_problem_t *ps, int32_t count, void *stream) {
     if (rc != GEMM_OK || plan.total_tiles == 0) return rc;
     hipStream_t s = (hipStream_t)stream;
     const GroupDesc *dd = nullptr;
+    int32_t *cnt = nullptr;
+    rc = stream_counters(s, &cnt);
+    if (rc != GEMM_OK) return rc;
     rc = upload_descs(plan, s, &dd);
     if (rc != GEMM_OK) return rc;
-    return enqueue_group(plan, dd, s);
+    return enqueue_group(plan, dd, cnt, s);
 }
 
 int gemm_grouped_graph_create(const gemm_problem_t *ps, int32_t count, void **graph_out) {
@@ -178,12 +216,17 @@ int gemm_grouped_graph_create(const gemm_problem_t *ps, int32_t count, void **gr
     if (plan.total_tiles > 0) {
         const size_t bytes = plan.descs.size() * sizeof(GroupDesc);
         hipStream_t cs = nullptr;
+        rc = alloc_counters(&g->counters);
+        if (rc != GEMM_OK) {
+            delete g;
+            return rc;
+        }
         hipError_t e = hipMalloc(&g->descs, bytes);
         if (e == hipSuccess) e = hipMemcpy(g->descs, plan.descs.data(), bytes, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            rc = enqueue_group(plan, static_cast<const GroupDesc *>(g->descs), cs);
+            rc = enqueue_group(plan, static_cast<const GroupDesc *>(g->descs), g->counters, cs);
             hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
             if (rc == GEMM_OK && e2 != hipSuccess) e = e2;
         }
@@ -193,6 +236,7 @@ int gemm_grouped_graph_create(const gemm_problem_t *ps, int32_t count, void **gr
             if (g->exec) (void)hipGraphExecDestroy(g->exec);
             if (g->graph) (void)hipGraphDestroy(g->graph);
             if (g->descs) (void)hipFree(g->descs);
+            if (g->counters) (void)hipFree(g->counters);
             delete g;
             if (rc != GEMM_OK) return rc;
             return fail(GEMM_EHIP, "graph capture failed: %s", hipGetErrorString(e));
@@ -222,6 +266,7 @@ int gemm_graph_destroy(void *graph) {
     }
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->descs) (void)hipFree(g->descs);
+    if (g->counters) (void)hipFree(g->counters);
     delete g;
     return GEMM_OK;
 }

@@ -24,7 +24,11 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan);
 // Copy the descriptors to the stream's device workspace (stream-ordered).
 int upload_descs(const GroupPlan &plan, hipStream_t s, const GroupDesc **dev_out);
 
-// Launch the persistent kernel over descriptors already on the device.
-int enqueue_group(const GroupPlan &plan, const GroupDesc *dev_descs, hipStream_t s);
+// Launch the persistent kernel over descriptors already on the device, with
+// zeroed work-queue counters (the launch leaves them zeroed again).
+int enqueue_group(const GroupPlan &plan, const GroupDesc *dev_descs, int32_t *counters, hipStream_t s);
+
+// 256 bytes of zeroed device memory for a grouped launch's work queue.
+int alloc_counters(int32_t **out);
 
 }  // namespace mg

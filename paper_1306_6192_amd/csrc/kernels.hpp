@@ -15,6 +15,10 @@ struct GroupedArgs {
     const GroupDesc *descs;
     int32_t count;
     int32_t total_tiles;
+    // Work queue: counters[0] = next tile to hand out, counters[1] = workgroups
+    // finished.  Both start at zero; the last workgroup to finish puts them
+    // back to zero, so a replay (or the next launch) finds them ready.
+    int32_t *counters;
 };
 
 typedef hipError_t (*PlainLaunchFn)(const TileProblem &P, int nwg, hipStream_t s);
@@ -43,6 +47,8 @@ struct GroupedKernel {
 // per-mode translation units).
 const KernelCfg *f32_configs(int *count);
 const KernelCfg *lp_configs(int mode, int *count);
+const KernelCfg *f64_configs(int *count);   // binary64 (plain launches only)
+const KernelCfg *c32_configs(int *count);   // complex float (plain launches only)
 const GroupedKernel *f32_grouped();
 const GroupedKernel *lp_grouped(int mode);
 
@@ -53,5 +59,10 @@ hipError_t launch_splitk_reduce(const float *ws, int64_t split_stride, int split
 hipError_t launch_convert_f32(const float *x, int64_t count, int to_mode, void *out, hipStream_t s);
 hipError_t launch_quantize_e4m3(const float *x, int64_t count, uint8_t *q, float *scale_out,
                                 uint32_t *amax_scratch, hipStream_t s);
+// Element-wise c = a + b or a - b (float or double, elem_bytes 4 or 8) and
+// the zero fill of the binary64 / complex forms (ew.hip).
+hipError_t launch_ew_add(int elem_bytes, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                         int64_t ldc, int m, int n, int subtract, hipStream_t s);
+hipError_t launch_zero_rows(void *C, int64_t ld_bytes, int m, int64_t row_bytes, hipStream_t s);
 hipError_t launch_errnorm(const float *C, int64_t ldc, const double *R, int64_t ldr, int64_t m,
                           int64_t n, double *out3, double *partials, int nparts, hipStream_t s);

@@ -32,14 +32,22 @@ __device__ __forceinline__ int group_find(const GroupDesc *d, int count, int t) 
 
 template <int A, int B> struct cmax { static constexpr int v = A > B ? A : B; };
 
-// Each workgroup takes tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... of
-// the concatenated tile lists; descriptor field `cfg` selects Cfg0 or Cfg1 for
-// that problem.  Every workgroup leaves the loop after the last tile, so the
-// grid always drains.
+// Persistent workgroups take tiles from a queue (one atomic increment per
+// tile) over the concatenated tile lists, which the host orders from the
+// costliest tile to the cheapest, so the tiles are handed out greedily,
+// longest first.  Descriptor field `cfg` selects Cfg0 or Cfg1 for a problem.
+// Every workgroup leaves the loop once the queue is exhausted, so the grid
+// always drains; the last one out resets the queue for the next launch.
 template <class Cfg0, class Cfg1, int OCC>
 __global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_grouped_kernel(GroupedArgs G) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[cmax<Cfg0::LDS_BYTES, Cfg1::LDS_BYTES>::v];
-    for (int t = blockIdx.x; t < G.total_tiles; t += gridDim.x) {
+    __shared__ int next_tile;
+    while (true) {
+        if (threadIdx.x == 0) next_tile = atomicAdd(&G.counters[0], 1);
+        __syncthreads();
+        const int t = next_tile;
+        __syncthreads();
+        if (t >= G.total_tiles) break;
         const int p = group_find(G.descs, G.count, t);
         const GroupDesc &d = G.descs[p];
         const TileProblem P = d.P;
@@ -51,6 +59,13 @@ __global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_grouped_kernel(Grouped
         } else {
             tile_coords(local, P.tiles_m, P.tiles_n, 8, tm, tn);
             Cfg1::run(P, tm, tn, 0, lds);
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&G.counters[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&G.counters[0], 0);
+            atomicExch(&G.counters[1], 0);
         }
     }
 }

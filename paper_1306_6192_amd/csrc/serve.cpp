@@ -52,6 +52,7 @@ struct Slot {
     void *host = nullptr;
     size_t host_bytes = 0;
     DevBuf ws;                           // split-K workspace (plain executor)
+    int32_t *counters = nullptr;         // grouped-launch work queue
     std::vector<Request *> running;      // empty = idle
     uint64_t fake_done_at = 0;
     bool fake_fail = false;
@@ -107,6 +108,8 @@ int Server::init() {
         for (Slot &s : slots) {
             MG_HIP(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
             MG_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+            int rc = alloc_counters(&s.counters);
+            if (rc != GEMM_OK) return rc;
         }
     }
     thread = std::thread([this] { loop(); });
@@ -233,7 +236,7 @@ int Server::launch_batch(Slot &s, std::vector<Request *> &b) {
         // the slot is idle: its previous upload has completed
         memcpy(s.host, plan.descs.data(), bytes);
         MG_HIP(hipMemcpyAsync(s.descs.ptr, s.host, bytes, hipMemcpyHostToDevice, s.stream));
-        rc = enqueue_group(plan, static_cast<const GroupDesc *>(s.descs.ptr), s.stream);
+        rc = enqueue_group(plan, static_cast<const GroupDesc *>(s.descs.ptr), s.counters, s.stream);
         if (rc != GEMM_OK) return rc;
     }
     MG_HIP(hipEventRecord(s.done, s.stream));
@@ -434,6 +437,7 @@ int gemm_serve_destroy(void *server) {
         if (sl.host) (void)hipHostFree(sl.host);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.counters) (void)hipFree(sl.counters);
     }
     for (auto &kv : s->by_ticket) delete kv.second;
     delete s;
