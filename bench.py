@@ -20,8 +20,12 @@ Secondary sections (extra keys of the same line; --sections to choose):
              [64, 4096], 50% FP32 / 35% BF16 / 15% E4M3, operands resident
              in HBM; p50/p99 latency and aggregate TFLOP/s per arrival rate,
              continuous batching vs plain FIFO launches.
+  ablation   the paper's global-memory and 16x16-LDS kernels beside the
+             matrix-core kernel, float 4096^3.
+  table2     the double and complex-float products at 4096^3 and 8192^3.
+  addition   float and double matrix addition/subtraction at 4096^2.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections plain,precision,grouped,serving]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections plain,precision,grouped,serving,...]
 """
 from __future__ import annotations
 
@@ -39,7 +43,7 @@ sys.path.insert(0, ROOT)
 
 SHAPES = [(2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192), (8192, 1024, 4096), (128, 8192, 8192)]
 DOMINANT = (8192, 8192, 8192)
-PEAK = {"f32": 157.3, "bf16": 2516.6, "f16": 2516.6, "e4m3": 5033.2}   # dense MFMA TFLOP/s
+PEAK = {"f32": 157.3, "bf16": 2516.6, "f16": 2516.6, "e4m3": 5033.2, "f64": 78.6}   # dense MFMA TFLOP/s
 
 
 def parse():
@@ -47,7 +51,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sections", default="plain,precision,grouped,serving,ablation")
+    ap.add_argument("--sections", default="plain,precision,grouped,serving,ablation,table2,addition")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--samples", type=int, default=512, help="sampled outputs per product for the error")
@@ -412,6 +416,90 @@ def section_ablation(args, torch, mg, synth, stream, line):
                              "paper_table2_c2050_seconds": {"global_memory": 2.49, "shared_memory": 0.83}}
 
 
+def section_table2(args, torch, mg, synth, stream, line):
+    """The paper's Table 2 columns at its size, m = n = k = 4096 (plus 8192^3):
+    the double product (binary64 MFMA) and the complex-float product (four
+    real FP32 MFMA products per complex term), seconds, TFLOP/s and the
+    fraction of the matching MFMA peak, with the sampled error against the
+    compensated (double) and binary64 complex oracles."""
+    import oracle
+    T = Timer(torch, stream)
+    out = []
+    for size in (4096, 8192):
+        g = synth.rng(92)
+        rows = g.integers(0, size, size=args.samples)
+        cols = g.integers(0, size, size=args.samples)
+        A, B = synth.pair64(size, size, size, seed=0)
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        C = torch.empty((size, size), dtype=torch.float64, device="cuda")
+        ms = T.time(lambda: mg.gemm_f64(dA, dB, out=C, stream=stream), 5, warmup=1)
+        avg = float(np.mean(ms))
+        R = oracle.gemm_dot2_sampled(A, B, rows, cols)
+        tf = 2.0 * size ** 3 / (avg / 1e3) / 1e12
+        out.append({"type": "double", "size": size, "seconds": round(avg / 1e3, 6), "tflops": round(tf, 2),
+                    "frac_peak": round(tf / PEAK["f64"], 4),
+                    "rel_err_sampled": float(oracle.relerr(C.cpu().numpy()[rows, cols], R))})
+        log(f"table2 {out[-1]}")
+        del dA, dB, C
+        A, B = synth.pair_c64(size, size, size, seed=0)
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        C = torch.empty((size, size), dtype=torch.complex64, device="cuda")
+        ms = T.time(lambda: mg.gemm_c32(dA, dB, out=C, stream=stream), 5, warmup=1)
+        avg = float(np.mean(ms))
+        R = oracle.gemm_c128_sampled(A, B, rows, cols)
+        tf = 8.0 * size ** 3 / (avg / 1e3) / 1e12      # real flops of the complex product
+        Ch = C.cpu().numpy()[rows, cols]
+        out.append({"type": "complex_float", "size": size, "seconds": round(avg / 1e3, 6),
+                    "tflops_real": round(tf, 2), "frac_peak": round(tf / PEAK["f32"], 4),
+                    "rel_err_sampled": float(oracle.relerr(Ch.view(np.float32), R.view(np.float64)))})
+        log(f"table2 {out[-1]}")
+        del dA, dB, C
+        torch.cuda.empty_cache()
+    line["table2"] = {"products": out,
+                      "paper_table2_c2050_shared_memory_seconds": {"float": 0.83, "double": 1.6,
+                                                                   "complex_float": 2.07}}
+
+
+def section_addition(args, torch, mg, synth, stream, line):
+    """Matrix addition and subtraction at the paper's size (4096 x 4096,
+    float and double; Results section, Fig. 9): device time, HBM GB/s (three
+    streams of the element size) against 8 TB/s, and the host CPU time one
+    call costs (the paper counts the host's instructions per kernel call; the
+    host's thread CPU clock stands in where no instruction counter is
+    exposed), beside a host-side addition of the same matrices."""
+    import time as _t
+    T = Timer(torch, stream)
+    res = []
+    for name, draw, es in (("float", synth.draw, 4), ("double", synth.draw64, 8)):
+        g = synth.rng(93)
+        A = draw(g, (4096, 4096))
+        B = draw(g, (4096, 4096))
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        C = torch.empty_like(dA)
+        for sub in (False, True):
+            ms = T.time(lambda: mg.add(dA, dB, out=C, subtract=sub, stream=stream), 20, warmup=3)
+            avg = float(np.mean(ms))
+            gbs = 3 * es * 4096 * 4096 / (avg / 1e3) / 1e9
+            torch.cuda.synchronize()
+            reps = 200
+            t0 = _t.thread_time_ns()
+            for _ in range(reps):
+                mg.add(dA, dB, out=C, subtract=sub, stream=stream)
+            host_us = (_t.thread_time_ns() - t0) / reps / 1e3
+            torch.cuda.synchronize()
+            t0 = _t.thread_time_ns()
+            Hc = A - B if sub else A + B
+            cpu_ms = (_t.thread_time_ns() - t0) / 1e6
+            ok = bool(np.array_equal(C.cpu().numpy(), Hc))
+            res.append({"type": name, "op": "sub" if sub else "add", "us": round(avg * 1e3, 2),
+                        "gb_per_s": round(gbs, 1), "frac_hbm_peak": round(gbs / 8000.0, 4),
+                        "host_cpu_us_per_call": round(host_us, 2), "host_numpy_cpu_ms": round(cpu_ms, 2),
+                        "matches_host": ok})
+            log(f"addition {res[-1]}")
+        del dA, dB, C
+    line["addition_4096"] = res
+
+
 def section_copy(args, torch, mg, synth, stream, line):
     """A plain device copy of known size: the reference for scaling the
     FETCH_SIZE / WRITE_SIZE counters of the product kernels."""
@@ -451,7 +539,8 @@ def main():
     for name in sections:
         log(f"section {name}")
         {"plain": section_plain, "precision": section_precision, "grouped": section_grouped,
-         "serving": section_serving, "copy": section_copy, "ablation": section_ablation}[name](args, torch, mg, synth, stream, line)
+         "serving": section_serving, "copy": section_copy, "ablation": section_ablation,
+         "table2": section_table2, "addition": section_addition}[name](args, torch, mg, synth, stream, line)
     print(json.dumps(line), flush=True)
 
 

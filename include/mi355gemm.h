@@ -64,10 +64,16 @@ typedef enum {
     GEMM_MODE_BF16 = 1,
     GEMM_MODE_F16 = 2,
     GEMM_MODE_F8E4M3 = 3,
-    GEMM_MODE_F32_SPLIT_BF16X3 = 4
+    GEMM_MODE_F32_SPLIT_BF16X3 = 4,
+    /* Kernel families with entry points of their own (gemm_plain_f64,
+     * gemm_plain_c32); they name configurations in gemm_num_configs /
+     * gemm_config_info and are not valid in a gemm_problem_t. */
+    GEMM_MODE_F64 = 5,
+    GEMM_MODE_C32 = 6
 } gemm_mode_t;
 
-#define GEMM_NUM_MODES 5
+#define GEMM_NUM_MODES 5            /* modes a gemm_problem_t may carry */
+#define GEMM_NUM_KERNEL_FAMILIES 7  /* modes gemm_num_configs accepts */
 
 /* One product problem (row-major; C = A*B, C overwritten). */
 typedef struct gemm_problem {
@@ -106,10 +112,48 @@ int gemm_plain_cfg(const gemm_problem_t *p, int32_t cfg, int32_t split_k, void *
  * (GEMM_EUNSUPPORTED for other modes). */
 int gemm_ablation(const gemm_problem_t *p, int32_t variant, void *stream);
 
-/* Number of tile configurations compiled for `mode`, and their geometry:
+/* Number of tile configurations compiled for `mode` (any of the
+ * GEMM_NUM_KERNEL_FAMILIES), and their geometry:
  * info[0..5] = {BM, BN, BK, waves, lds_bytes, mfma_k}. */
 int gemm_num_configs(int32_t mode);
 int gemm_config_info(int32_t mode, int32_t cfg, int32_t info[6]);
+
+/* ---------------------------------------------------------------------- */
+/* Double and complex-float products, matrix addition (the paper times the */
+/* product for float, double and complex float matrices, Results section,  */
+/* Table 2, and analyses matrix addition/subtraction beside it, Fig. 9).    */
+
+/* C = A*B in binary64: A (m x k), B (k x n), C (m x n) are double, row-major,
+ * strides in elements.  Products and sums are binary64 operations on the
+ * matrix cores (v_mfma_f64_16x16x4_f64); summation order is unspecified, so
+ * each c_ij is within (k+2) 2^-53 (|A||B|)_ij of the exact value.  The tile
+ * configuration is chosen from the shape; there is no split-K.  Same
+ * validation and errors as gemm_plain (C must not overlap A or B); k == 0
+ * zeroes C. */
+int gemm_plain_f64(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *B, int64_t ldb,
+                   double *C, int64_t ldc, void *stream);
+/* As gemm_plain_f64 with an explicit configuration (gemm_config_info of
+ * GEMM_MODE_F64).  For tests. */
+int gemm_plain_f64_cfg(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *B,
+                       int64_t ldb, double *C, int64_t ldc, int32_t cfg, void *stream);
+
+/* C = A*B over complex float: every element is an interleaved (re, im) pair
+ * of float32 (8 bytes; C99 float _Complex layout), strides count COMPLEX
+ * elements.  Each complex multiply-add is four real float32 MFMA products
+ * (Re += ar br - ai bi, Im += ar bi + ai br) accumulated in float32.  No
+ * split-K; same validation and errors as gemm_plain_f64. */
+int gemm_plain_c32(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B, int64_t ldb,
+                   float *C, int64_t ldc, void *stream);
+int gemm_plain_c32_cfg(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B,
+                       int64_t ldb, float *C, int64_t ldc, int32_t cfg, void *stream);
+
+/* c_ij = a_ij + b_ij (subtract == 0) or a_ij - b_ij (subtract != 0), one
+ * IEEE operation per element.  `dtype` is GEMM_MODE_F32 (float) or
+ * GEMM_MODE_F64 (double); A, B, C are m x n with strides in elements
+ * (>= max(1, n)).  C may be A or B itself (same stride: in place); any other
+ * overlap is GEMM_EINVAL.  m == 0 or n == 0 is a no-op. */
+int gemm_add(int32_t dtype, int32_t subtract, int64_t m, int64_t n, const void *A, int64_t lda, const void *B,
+             int64_t ldb, void *C, int64_t ldc, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Operand preparation (the reduced-precision forms' input conversion).    */

@@ -11,12 +11,12 @@ import ctypes
 
 from . import _lib
 from ._lib import (GEMM_EBUSY, GEMM_EINVAL, GEMM_ENOMEM, GEMM_EUNSUPPORTED, GEMM_OK, GEMM_PENDING,
-                   MODE_BF16, MODE_F8E4M3, MODE_F16, MODE_F32, MODE_NAMES, MODE_SPLIT_BF16X3, GemmError,
-                   check, load)
+                   MODE_BF16, MODE_C32, MODE_F8E4M3, MODE_F16, MODE_F32, MODE_F64, MODE_NAMES, MODE_SPLIT_BF16X3,
+                   GemmError, check, load)
 
-__all__ = ["gemm", "convert", "quantize_e4m3", "errnorm", "grouped", "GroupedGraph", "Server", "tune",
+__all__ = ["gemm", "gemm_f64", "gemm_c32", "add", "convert", "quantize_e4m3", "errnorm", "grouped", "GroupedGraph", "Server", "tune",
            "tuner_lookup", "config_info", "num_configs", "GemmError", "MODE_F32", "MODE_BF16", "MODE_F16",
-           "MODE_F8E4M3", "MODE_SPLIT_BF16X3", "MODE_NAMES", "load"]
+           "MODE_F8E4M3", "MODE_SPLIT_BF16X3", "MODE_F64", "MODE_C32", "MODE_NAMES", "load"]
 
 
 def _torch():
@@ -88,6 +88,63 @@ def gemm(A, B, out=None, mode=MODE_F32, scale_a=1.0, scale_b=1.0, cfg=None, spli
             cfg = c if cfg is None else cfg
             split_k = s if split_k is None else split_k
         check(lib.gemm_plain_cfg(ctypes.byref(p), int(cfg), int(split_k), _stream_ptr(stream)))
+    return out
+
+
+def _gemm_same_type(A, B, out, dtype, entry, cfg, stream):
+    torch = _torch()
+    for t, name in ((A, "A"), (B, "B")):
+        _check_mat(t, name)
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if A.shape[1] != B.shape[0]:
+        raise ValueError(f"inner dimensions differ: {tuple(A.shape)} @ {tuple(B.shape)}")
+    m, k = A.shape
+    n = B.shape[1]
+    if out is None:
+        out = torch.empty((m, n), dtype=dtype, device=A.device)
+    _check_mat(out, "out")
+    if out.dtype != dtype or tuple(out.shape) != (m, n):
+        raise ValueError(f"out must be {dtype} of shape (m, n)")
+    lib = load()
+    args = (m, n, k, A.data_ptr() or None, _ld(A), B.data_ptr() or None, _ld(B), out.data_ptr() or None, _ld(out))
+    if cfg is None:
+        check(getattr(lib, entry)(*args, _stream_ptr(stream)))
+    else:
+        check(getattr(lib, entry + "_cfg")(*args, int(cfg), _stream_ptr(stream)))
+    return out
+
+
+def gemm_f64(A, B, out=None, cfg=None, stream=None):
+    """C = A @ B in binary64 for float64 device matrices (gemm_plain_f64)."""
+    return _gemm_same_type(A, B, out, _torch().float64, "gemm_plain_f64", cfg, stream)
+
+
+def gemm_c32(A, B, out=None, cfg=None, stream=None):
+    """C = A @ B over complex float for complex64 device matrices
+    (gemm_plain_c32; four real float32 products per complex term)."""
+    return _gemm_same_type(A, B, out, _torch().complex64, "gemm_plain_c32", cfg, stream)
+
+
+def add(A, B, out=None, subtract=False, stream=None):
+    """C = A + B (or A - B) element-wise for float32 or float64 device
+    matrices (gemm_add); ``out`` may be A or B for an in-place update."""
+    torch = _torch()
+    for t, name in ((A, "A"), (B, "B")):
+        _check_mat(t, name)
+    if A.dtype != B.dtype or A.dtype not in (torch.float32, torch.float64):
+        raise TypeError("A and B must both be float32 or both float64")
+    if A.shape != B.shape:
+        raise ValueError(f"shapes differ: {tuple(A.shape)} vs {tuple(B.shape)}")
+    if out is None:
+        out = torch.empty_like(A)
+    _check_mat(out, "out")
+    if out.dtype != A.dtype or out.shape != A.shape:
+        raise ValueError("out must match A in dtype and shape")
+    m, n = A.shape
+    dtype = MODE_F64 if A.dtype == torch.float64 else MODE_F32
+    check(load().gemm_add(dtype, 1 if subtract else 0, m, n, A.data_ptr() or None, _ld(A), B.data_ptr() or None,
+                          _ld(B), out.data_ptr() or None, _ld(out), _stream_ptr(stream)))
     return out
 
 

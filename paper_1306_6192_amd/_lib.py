@@ -30,8 +30,12 @@ MODE_BF16 = 1
 MODE_F16 = 2
 MODE_F8E4M3 = 3
 MODE_SPLIT_BF16X3 = 4
+MODE_F64 = 5   # kernel family of gemm_plain_f64 (not a problem mode)
+MODE_C32 = 6   # kernel family of gemm_plain_c32 (not a problem mode)
+NUM_MODES = 5
+NUM_KERNEL_FAMILIES = 7
 MODE_NAMES = {MODE_F32: "f32", MODE_BF16: "bf16", MODE_F16: "f16", MODE_F8E4M3: "e4m3",
-              MODE_SPLIT_BF16X3: "split_bf16x3"}
+              MODE_SPLIT_BF16X3: "split_bf16x3", MODE_F64: "f64", MODE_C32: "c32"}
 ELEM_SIZE = {MODE_F32: 4, MODE_BF16: 2, MODE_F16: 2, MODE_F8E4M3: 1, MODE_SPLIT_BF16X3: 4}
 
 
@@ -73,6 +77,16 @@ _SIGS = {
     "gemm_plain": (c_int32, [_P, c_void_p]),
     "gemm_plain_cfg": (c_int32, [_P, c_int32, c_int32, c_void_p]),
     "gemm_ablation": (c_int32, [_P, c_int32, c_void_p]),
+    "gemm_plain_f64": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                 c_int64, c_void_p]),
+    "gemm_plain_f64_cfg": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                     c_int64, c_int32, c_void_p]),
+    "gemm_plain_c32": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                 c_int64, c_void_p]),
+    "gemm_plain_c32_cfg": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                     c_int64, c_int32, c_void_p]),
+    "gemm_add": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                           c_int64, c_void_p]),
     "gemm_num_configs": (c_int32, [c_int32]),
     "gemm_config_info": (c_int32, [c_int32, c_int32, POINTER(c_int32)]),
     "gemm_convert_f32": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p]),

@@ -100,6 +100,8 @@ int num_cus() {
 
 const KernelCfg *configs(int mode, int *count) {
     if (mode == GEMM_MODE_F32) return f32_configs(count);
+    if (mode == GEMM_MODE_F64) return f64_configs(count);
+    if (mode == GEMM_MODE_C32) return c32_configs(count);
     return lp_configs(mode, count);
 }
 
@@ -256,7 +258,7 @@ uint64_t gemm_now_ns(void) { return now_ns(); }
 
 int gemm_num_configs(int32_t mode) {
     clear_error();
-    if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
+    if (mode < 0 || mode >= GEMM_NUM_KERNEL_FAMILIES) return fail(GEMM_EINVAL, "unknown mode %d", mode);
     int count = 0;
     configs(mode, &count);
     return count;
@@ -264,7 +266,7 @@ int gemm_num_configs(int32_t mode) {
 
 int gemm_config_info(int32_t mode, int32_t cfg, int32_t info[6]) {
     clear_error();
-    if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
+    if (mode < 0 || mode >= GEMM_NUM_KERNEL_FAMILIES) return fail(GEMM_EINVAL, "unknown mode %d", mode);
     if (!info) return fail(GEMM_EINVAL, "info is NULL");
     int count = 0;
     const KernelCfg *t = configs(mode, &count);

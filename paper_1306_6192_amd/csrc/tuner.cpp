@@ -52,7 +52,9 @@ void heuristic_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg_out, i
         const double bonus = kc.chunk ? 1.7 : 1.0;
         const int64_t tiles = ((m + kc.bm - 1) / kc.bm) * ((n + kc.bn - 1) / kc.bn);
         const int64_t nkt = (k + split_grain(mode) - 1) / split_grain(mode) * (split_grain(mode) / kc.bk);
-        for (int split = 1; split <= 16; split *= 2) {
+        // the binary64 and complex families have no split-K
+        const int max_split = mode < GEMM_NUM_MODES ? 16 : 1;
+        for (int split = 1; split <= max_split; split *= 2) {
             if (split > 1 && nkt / split < 4) break;
             const int64_t per = (nkt + split - 1) / split;
             const int64_t wgs = tiles * split;

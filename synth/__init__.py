@@ -4,7 +4,9 @@ checks.
 This module holds no arithmetic of the product itself: it only draws numbers.
 Every generator is ``numpy.random.default_rng(seed)``-based so a (shape,
 distribution, seed) triple names one input exactly.  Values are drawn in
-binary64 and rounded to float32 (RNE, numpy's cast).
+binary64 and rounded to float32 (RNE, numpy's cast); ``draw64``/``pair64``
+keep the binary64 values and ``draw_c64``/``pair_c64`` give complex64
+matrices (real parts drawn before imaginary parts).
 
 Distributions (the paper prints no input values; these are the workloads'
 stated recipes):
@@ -29,8 +31,8 @@ def rng(seed: int) -> np.random.Generator:
     return np.random.default_rng(seed)
 
 
-def draw(g: np.random.Generator, shape, dist: str = "uniform", R: int = 16) -> np.ndarray:
-    """One float32 matrix from generator ``g`` (advances ``g``)."""
+def draw64(g: np.random.Generator, shape, dist: str = "uniform", R: int = 16) -> np.ndarray:
+    """One binary64 matrix from generator ``g`` (advances ``g``), not rounded."""
     if dist == "uniform":
         x = g.uniform(-1.0, 1.0, size=shape)
     elif dist == "normal":
@@ -47,7 +49,24 @@ def draw(g: np.random.Generator, shape, dist: str = "uniform", R: int = 16) -> n
         x = g.integers(-R, R + 1, size=shape).astype(np.float64)
     else:
         raise ValueError(f"unknown distribution {dist!r}")
-    return x.astype(np.float32)
+    return x.astype(np.float64)
+
+
+def draw(g: np.random.Generator, shape, dist: str = "uniform", R: int = 16) -> np.ndarray:
+    """One float32 matrix from generator ``g`` (advances ``g``): draw64 rounded
+    to float32."""
+    return draw64(g, shape, dist, R).astype(np.float32)
+
+
+def draw_c64(g: np.random.Generator, shape, dist: str = "uniform", R: int = 16) -> np.ndarray:
+    """One complex64 matrix: the real parts are drawn first, then the
+    imaginary parts, each as ``draw``."""
+    re = draw(g, shape, dist, R)
+    im = draw(g, shape, dist, R)
+    out = np.empty(shape, dtype=np.complex64)
+    out.real = re
+    out.imag = im
+    return out
 
 
 def pair(m: int, n: int, k: int, seed: int = 0, dist: str = "uniform", R: int = 16):
@@ -56,6 +75,18 @@ def pair(m: int, n: int, k: int, seed: int = 0, dist: str = "uniform", R: int = 
     A = draw(g, (m, k), dist, R)
     B = draw(g, (k, n), dist, R)
     return A, B
+
+
+def pair64(m: int, n: int, k: int, seed: int = 0, dist: str = "uniform", R: int = 16):
+    """(A, B) in binary64 (A first), for the double-precision product."""
+    g = rng(seed)
+    return draw64(g, (m, k), dist, R), draw64(g, (k, n), dist, R)
+
+
+def pair_c64(m: int, n: int, k: int, seed: int = 0, dist: str = "uniform", R: int = 16):
+    """(A, B) complex64 (A first), for the complex-float product."""
+    g = rng(seed)
+    return draw_c64(g, (m, k), dist, R), draw_c64(g, (k, n), dist, R)
 
 
 def loguniform_dims(count: int, lo: int, hi: int, seed: int = 0) -> np.ndarray:

@@ -50,6 +50,8 @@ BAD = [
     (dict(ldb=4), "ldb"),
     (dict(ldc=4), "ldc"),
     (dict(mode=7), "mode"),
+    (dict(mode=5), "mode"),   # binary64 and complex have entry points of their own
+    (dict(mode=6), "mode"),
     (dict(mode=-1), "mode"),
     (dict(flags=1), "flags"),
     (dict(C=None), "C is NULL"),
@@ -151,3 +153,69 @@ def test_misc_entry_points_validate():
     assert lib.gemm_quantize_e4m3(A_PTR, 10, B_PTR, None, None) == _lib.GEMM_EINVAL
     assert lib.gemm_errnorm(A_PTR, 3, B_PTR, 3, 2, 4, C_PTR, None) == _lib.GEMM_EINVAL
     assert lib.gemm_errnorm(A_PTR, 4, B_PTR, 4, 2, 4, None, None) == _lib.GEMM_EINVAL
+
+
+EXT = ["gemm_plain_f64", "gemm_plain_c32"]
+
+
+def _ext_args(**kw):
+    d = dict(m=4, n=5, k=6, A=A_PTR, lda=6, B=B_PTR, ldb=5, C=C_PTR, ldc=5)
+    d.update(kw)
+    return [d["m"], d["n"], d["k"], d["A"], d["lda"], d["B"], d["ldb"], d["C"], d["ldc"]]
+
+
+EXT_BAD = [
+    (dict(m=-1), "negative"),
+    (dict(lda=5), "lda"),
+    (dict(ldb=4), "ldb"),
+    (dict(ldc=4), "ldc"),
+    (dict(C=None), "C is NULL"),
+    (dict(A=None), "NULL"),
+    (dict(C=A_PTR + 8), "overlap"),
+    (dict(C=B_PTR - 16), "overlap"),
+]
+
+
+@pytest.mark.parametrize("entry", EXT)
+@pytest.mark.parametrize("kw,msg", EXT_BAD)
+def test_f64_c32_reject_bad_arguments(entry, kw, msg):
+    lib = _lib.load()
+    assert getattr(lib, entry)(*_ext_args(**kw), None) == _lib.GEMM_EINVAL
+    assert msg.lower() in _lib.last_error().lower()
+    assert getattr(lib, entry + "_cfg")(*_ext_args(**kw), 0, None) == _lib.GEMM_EINVAL
+
+
+@pytest.mark.parametrize("entry", EXT)
+def test_f64_c32_empty_output_and_bad_config(entry):
+    lib = _lib.load()
+    assert getattr(lib, entry)(*_ext_args(m=0, A=None, C=None), None) == _lib.GEMM_OK
+    assert getattr(lib, entry + "_cfg")(*_ext_args(), -1, None) == _lib.GEMM_EINVAL
+    assert getattr(lib, entry + "_cfg")(*_ext_args(), 99, None) == _lib.GEMM_EINVAL
+
+
+def test_f64_c32_config_tables():
+    lib = _lib.load()
+    info = (ctypes.c_int32 * 6)()
+    for mode, mk in ((_lib.MODE_F64, 4), (_lib.MODE_C32, 2)):
+        n = lib.gemm_num_configs(mode)
+        assert n >= 2
+        for c in range(n):
+            assert lib.gemm_config_info(mode, c, info) == 0
+            assert info[2] == 16 and info[3] == 4 and info[5] == mk and 0 < info[4] <= 160 * 1024
+    assert lib.gemm_num_configs(_lib.NUM_KERNEL_FAMILIES) == _lib.GEMM_EINVAL
+    c, s = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.gemm_tuner_lookup(_lib.MODE_F64, 4096, 4096, 4096, ctypes.byref(c), ctypes.byref(s)) == \
+        _lib.GEMM_EINVAL   # no gemm_problem_t mode: the lookup is for problem modes
+
+
+def test_add_validates():
+    lib = _lib.load()
+    F32, F64 = _lib.MODE_F32, _lib.MODE_F64
+    assert lib.gemm_add(1, 0, 4, 5, A_PTR, 5, B_PTR, 5, C_PTR, 5, None) == _lib.GEMM_EUNSUPPORTED
+    assert lib.gemm_add(F32, 0, -1, 5, A_PTR, 5, B_PTR, 5, C_PTR, 5, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_add(F32, 0, 4, 5, A_PTR, 4, B_PTR, 5, C_PTR, 5, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_add(F64, 0, 4, 5, A_PTR, 5, None, 5, C_PTR, 5, None) == _lib.GEMM_EINVAL
+    # partial overlap is rejected, exact aliasing (in place) passes validation
+    assert lib.gemm_add(F32, 0, 4, 5, A_PTR, 5, B_PTR, 5, A_PTR + 4, 5, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_add(F64, 1, 4, 5, A_PTR, 5, B_PTR, 5, B_PTR, 6, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_add(F32, 0, 0, 5, None, 5, None, 5, None, 5, None) == _lib.GEMM_OK
