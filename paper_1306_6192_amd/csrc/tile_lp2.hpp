@@ -87,10 +87,15 @@ struct Lp2Cfg {
 // pipeline waits for it explicitly (wait_vmcnt before the k-tile's barrier).
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm"
-__device__ __forceinline__ void load_lds16(const void *src, uint8_t *lds) {
-    uint32_t dst = (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t *)lds);
-    dst = __builtin_amdgcn_readfirstlane(dst);
+__device__ __forceinline__ void load_lds16(const void *src, uint32_t dst) {
     asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(dst), "v"(src) : "memory", "m0");
+}
+
+// LDS byte address of a pointer into the workgroup's shared array, made
+// wave-uniform (one conversion per tile, not per load).
+__device__ __forceinline__ uint32_t lds_addr(const uint8_t *p) {
+    const uint32_t a = (uint32_t)(uintptr_t)((const __attribute__((address_space(3))) uint8_t *)p);
+    return __builtin_amdgcn_readfirstlane(a);
 }
 #pragma clang diagnostic pop
 
@@ -104,12 +109,14 @@ struct Lp2Src {
     int bk[Cfg::B_LOADS];             // kr
     int64_t bstep;                    // bytes between consecutive B rows
     int kend;                         // loads at k >= kend read the zero chunk
+    uint32_t dst_a, dst_b;            // this wave's first A / B destination in stage 0
 };
 
 template <class Cfg>
-__device__ __forceinline__ void lp2_sources(const TileProblem &P, int m0, int n0, int kend, Lp2Src<Cfg> &S) {
+__device__ __forceinline__ void lp2_sources(const TileProblem &P, int m0, int n0, int kend, const uint8_t *lds,
+                                            Lp2Src<Cfg> &S) {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint8_t *A = static_cast<const uint8_t *>(P.A);
     const uint8_t *B = static_cast<const uint8_t *>(P.B);
 #pragma unroll
@@ -132,26 +139,33 @@ __device__ __forceinline__ void lp2_sources(const TileProblem &P, int m0, int n0
     }
     S.bstep = P.ldb * Cfg::ESZ;
     S.kend = kend;
+    const uint32_t base = lds_addr(lds);
+    S.dst_a = base + 1024 * (wave * Cfg::A_LOADS);
+    S.dst_b = base + Cfg::A_STAGE + 1024 * (wave * Cfg::B_LOADS);
 }
 
-// Issue this wave's direct loads of the k-tile starting at k0 into `stage`.
-template <class Cfg>
-__device__ __forceinline__ void lp2_issue(const Lp2Src<Cfg> &S, int k0, uint8_t *stage) {
-    const int wave = threadIdx.x >> 6;
-    const void *zero = g_zero_chunk;
-    const int64_t aoff = (int64_t)k0 * Cfg::ESZ;
-    const int64_t boff = (int64_t)k0 * S.bstep;
-#pragma unroll
-    for (int j = 0; j < Cfg::A_LOADS; ++j) {
-        const void *src = (k0 + S.ak[j] < S.kend) ? (const void *)(S.a[j] + aoff) : zero;
-        load_lds16(src, stage + 1024 * (wave * Cfg::A_LOADS + j));
+// Issue direct load j (A loads first, then B) of this wave for the k-tile
+// starting at k0 into the stage at LDS byte offset `soff`.  CHECK: chunks at
+// k >= kend read the zero chunk; without it the caller guarantees that the
+// whole k-tile lies before kend.
+template <class Cfg, bool CHECK>
+__device__ __forceinline__ void lp2_issue_one(const Lp2Src<Cfg> &S, int k0, uint32_t soff, int j) {
+    if (j < Cfg::A_LOADS) {
+        const void *src = (!CHECK || k0 + S.ak[j] < S.kend) ? (const void *)(S.a[j] + (int64_t)k0 * Cfg::ESZ)
+                                                             : (const void *)g_zero_chunk;
+        load_lds16(src, S.dst_a + soff + 1024 * j);
+    } else {
+        const int b = j - Cfg::A_LOADS;
+        const void *src = (!CHECK || k0 + S.bk[b] < S.kend) ? (const void *)(S.b[b] + (int64_t)k0 * S.bstep)
+                                                             : (const void *)g_zero_chunk;
+        load_lds16(src, S.dst_b + soff + 1024 * b);
     }
-    uint8_t *Bs = stage + Cfg::A_STAGE;
+}
+
+template <class Cfg, bool CHECK = true>
+__device__ __forceinline__ void lp2_issue(const Lp2Src<Cfg> &S, int k0, uint32_t soff) {
 #pragma unroll
-    for (int j = 0; j < Cfg::B_LOADS; ++j) {
-        const void *src = (k0 + S.bk[j] < S.kend) ? (const void *)(S.b[j] + boff) : zero;
-        load_lds16(src, Bs + 1024 * (wave * Cfg::B_LOADS + j));
-    }
+    for (int j = 0; j < Cfg::LOADS; ++j) lp2_issue_one<Cfg, CHECK>(S, k0, soff, j);
 }
 
 // MFMA operand fragments of one k-step (KCH consecutive k) for the wave's
@@ -169,9 +183,10 @@ struct Lp2Frag<Cfg, true> {
     i32x8 b[Cfg::CB];
 };
 
-// Read the fragments of k-step kc of the k-tile held in `stage`.
+// Read piece p of the fragments of k-step kc of the k-tile held in `stage`:
+// p < RB is A row block p, otherwise B column block p - RB.
 template <class Cfg>
-__device__ __forceinline__ void lp2_read(const uint8_t *stage, int kc, Lp2Frag<Cfg> &F) {
+__device__ __forceinline__ void lp2_read_piece(const uint8_t *stage, int kc, int p, Lp2Frag<Cfg> &F) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
@@ -180,17 +195,16 @@ __device__ __forceinline__ void lp2_read(const uint8_t *stage, int kc, Lp2Frag<C
     const uint8_t *As = stage;
     const uint8_t *Bs = stage + Cfg::A_STAGE;
     if constexpr (Cfg::MODE == GEMM_MODE_F8E4M3) {
-#pragma unroll
-        for (int rb = 0; rb < Cfg::RB; ++rb) {
+        if (p < Cfg::RB) {
+            const int rb = p;
             const int r = wm * Cfg::TM + rb * 32 + l32;
             const uint8_t *row = As + r * Cfg::A_ROWB;
             const u32x4 lo = *reinterpret_cast<const u32x4 *>(row + 16 * ((2 * g) ^ Cfg::a_swz(r)));
             const u32x4 hi = *reinterpret_cast<const u32x4 *>(row + 16 * ((2 * g + 1) ^ Cfg::a_swz(r)));
             F.a[rb] = (i32x8){(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
                               (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
-        }
-#pragma unroll
-        for (int cb = 0; cb < Cfg::CB; ++cb) {
+        } else {
+            const int cb = p - Cfg::RB;
             const int n = wn * Cfg::TN + cb * 32 + 16 * (G & 1) + 8 * (p16 & 1);
             i32x2 q[4];
 #pragma unroll
@@ -202,13 +216,12 @@ __device__ __forceinline__ void lp2_read(const uint8_t *stage, int kc, Lp2Frag<C
             F.b[cb] = (i32x8){q[0][0], q[0][1], q[1][0], q[1][1], q[2][0], q[2][1], q[3][0], q[3][1]};
         }
     } else {
-#pragma unroll
-        for (int rb = 0; rb < Cfg::RB; ++rb) {
+        if (p < Cfg::RB) {
+            const int rb = p;
             const int r = wm * Cfg::TM + rb * 32 + l32;
             F.a[rb] = *reinterpret_cast<const u32x4 *>(As + r * Cfg::A_ROWB + 16 * ((2 * kc + g) ^ Cfg::a_swz(r)));
-        }
-#pragma unroll
-        for (int cb = 0; cb < Cfg::CB; ++cb) {
+        } else {
+            const int cb = p - Cfg::RB;
             const int n = wn * Cfg::TN + cb * 32 + 16 * (G & 1) + 4 * (p16 & 3);
             s16x4 hv[2];
 #pragma unroll
@@ -224,23 +237,24 @@ __device__ __forceinline__ void lp2_read(const uint8_t *stage, int kc, Lp2Frag<C
     }
 }
 
-// MFMAs of accumulator rows [RB0, RB1) for one k-step.
-template <class Cfg, int RB0, int RB1>
-__device__ __forceinline__ void lp2_mfma(const Lp2Frag<Cfg> &F, f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+template <class Cfg>
+__device__ __forceinline__ void lp2_read(const uint8_t *stage, int kc, Lp2Frag<Cfg> &F) {
 #pragma unroll
-    for (int rb = RB0; rb < RB1; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < Cfg::CB; ++cb) {
-            if constexpr (Cfg::MODE == GEMM_MODE_F8E4M3)
-                acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(F.a[rb], F.b[cb], acc[rb][cb], 0, 0,
-                                                                             0, 0, 0, 0);
-            else if constexpr (Cfg::MODE == GEMM_MODE_BF16)
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                    __builtin_bit_cast(bf16x8, F.a[rb]), __builtin_bit_cast(bf16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
-            else
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                    __builtin_bit_cast(f16x8, F.a[rb]), __builtin_bit_cast(f16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
-        }
+    for (int p = 0; p < Cfg::RB + Cfg::CB; ++p) lp2_read_piece<Cfg>(stage, kc, p, F);
+}
+
+// The MFMA of accumulator block (rb, cb) for one k-step.
+template <class Cfg>
+__device__ __forceinline__ void lp2_mfma1(const Lp2Frag<Cfg> &F, f32x16 (&acc)[Cfg::RB][Cfg::CB], int rb, int cb) {
+    if constexpr (Cfg::MODE == GEMM_MODE_F8E4M3)
+        acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(F.a[rb], F.b[cb], acc[rb][cb], 0, 0, 0, 0,
+                                                                     0, 0);
+    else if constexpr (Cfg::MODE == GEMM_MODE_BF16)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            __builtin_bit_cast(bf16x8, F.a[rb]), __builtin_bit_cast(bf16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
+    else
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+            __builtin_bit_cast(f16x8, F.a[rb]), __builtin_bit_cast(f16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
 }
 
 // Natural-column epilogue: lane l%32 of accumulator block cb holds output
@@ -269,64 +283,91 @@ __device__ __forceinline__ void lp2_epilogue(float *__restrict__ C, int64_t ldc,
 
 // One k-step of the software pipeline, in one of two fixed forms so that the
 // loop body has no data-dependent branches:
-//   * inner step (the next step reads the same k-tile): read the next
-//     fragments, then issue this step's MFMAs;
-//   * boundary step (the next step starts a new k-tile): issue half of the
-//     MFMAs, retire this wave's LDS reads, wait for this wave's loads of the
-//     next k-tile, synchronise the workgroup (which publishes that k-tile and
-//     frees the stage just consumed), refill the freed stage with the k-tile
-//     STAGES ahead, read the next fragments and issue the other half.
+//   * inner step (the next step reads the same k-tile): this step's MFMAs,
+//     each followed by one piece of the next step's fragment reads;
+//   * boundary step (the next step starts a new k-tile): the first half of
+//     the MFMAs, retire this wave's LDS reads, wait for this wave's loads of
+//     the next k-tile, synchronise the workgroup (which publishes that k-tile
+//     and frees the stage just consumed), then the other half of the MFMAs
+//     interleaved with the reads of the next k-tile's first fragments and
+//     the refill of the freed stage with the k-tile STAGES ahead.
+// Scheduling barriers pin this interleaving: the matrix cores then always
+// have an MFMA queued while the wave issues its reads and loads, and the
+// compiler cannot sink MFMAs below the workgroup barrier (they touch no
+// memory) or pile the reads up in front of the boundary's LDS wait.
 // `i` is the k-tile and `u` = i mod STAGES its stage; the callers unroll over
 // u, so every LDS address is a constant offset from a few base registers.
 // Loads are issued for k-tiles past the end too (their sources are the zero
 // chunk), which keeps the number of loads in flight, and so every wait, the
-// same in every iteration.
-template <class Cfg, bool BOUNDARY>
+// same in every iteration.  CHECK selects the k-bounded form of the loads.
+template <class Cfg, bool BOUNDARY, bool CHECK>
 __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, int u, int kc, uint8_t *lds,
                                          const Lp2Frag<Cfg> &cur, Lp2Frag<Cfg> &nxt,
                                          f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
-    constexpr int H = (Cfg::RB + 1) / 2;
+    constexpr int NP = Cfg::RB + Cfg::CB;           // fragment pieces per step
+    constexpr int NM = Cfg::RB * Cfg::CB;           // MFMAs per step
     if constexpr (BOUNDARY) {
-        lp2_mfma<Cfg, 0, H>(cur, acc);
+        constexpr int H = ((Cfg::RB + 1) / 2) * Cfg::CB;   // MFMAs before the barrier
+        constexpr int W = NP + Cfg::LOADS;                 // work items after it
+        constexpr int PER = (W + (NM - H) - 1) / (NM - H);
+#pragma unroll
+        for (int t = 0; t < H; ++t) lp2_mfma1<Cfg>(cur, acc, t / Cfg::CB, t % Cfg::CB);
+        __builtin_amdgcn_sched_barrier(0);
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         wait_vmcnt<(Cfg::STAGES - 2) * Cfg::LOADS>();
         __syncthreads();
-        lp2_issue<Cfg>(S, (kt0 + i + Cfg::STAGES) * Cfg::BK, lds + u * Cfg::STAGE);
-        lp2_read<Cfg>(lds + ((u + 1) % Cfg::STAGES) * Cfg::STAGE, 0, nxt);
-        lp2_mfma<Cfg, H, Cfg::RB>(cur, acc);
+        const uint8_t *next = lds + ((u + 1) % Cfg::STAGES) * Cfg::STAGE;
+        const int k0 = (kt0 + i + Cfg::STAGES) * Cfg::BK;
+#pragma unroll
+        for (int t = H; t < NM; ++t) {
+            lp2_mfma1<Cfg>(cur, acc, t / Cfg::CB, t % Cfg::CB);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int w = (t - H) * PER; w < (t - H + 1) * PER && w < W; ++w) {
+                if (w < NP) lp2_read_piece<Cfg>(next, 0, w, nxt);
+                else lp2_issue_one<Cfg, CHECK>(S, k0, u * Cfg::STAGE, w - NP);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
     } else {
-        lp2_read<Cfg>(lds + u * Cfg::STAGE, kc + 1, nxt);
-        lp2_mfma<Cfg, 0, Cfg::RB>(cur, acc);
+        const uint8_t *here = lds + u * Cfg::STAGE;
+#pragma unroll
+        for (int t = 0; t < NM; ++t) {
+            lp2_mfma1<Cfg>(cur, acc, t / Cfg::CB, t % Cfg::CB);
+            __builtin_amdgcn_sched_barrier(0);
+            if (t < NP) lp2_read_piece<Cfg>(here, kc + 1, t, nxt);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 }
 
 // All steps of k-tile i (stage u).  On entry `fa` holds the tile's step-0
 // fragments; on exit the next tile's step-0 fragments are in `fa` (two steps
 // per k-tile) or in `fb` (one step).
-template <class Cfg>
+template <class Cfg, bool CHECK>
 __device__ __forceinline__ void lp2_ktile(const Lp2Src<Cfg> &S, int kt0, int i, int u, uint8_t *lds,
                                           Lp2Frag<Cfg> &fa, Lp2Frag<Cfg> &fb, f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
     if constexpr (Cfg::STEPS == 2) {
-        lp2_step<Cfg, false>(S, kt0, i, u, 0, lds, fa, fb, acc);
-        lp2_step<Cfg, true>(S, kt0, i, u, 1, lds, fb, fa, acc);
+        lp2_step<Cfg, false, CHECK>(S, kt0, i, u, 0, lds, fa, fb, acc);
+        lp2_step<Cfg, true, CHECK>(S, kt0, i, u, 1, lds, fb, fa, acc);
     } else {
-        lp2_step<Cfg, true>(S, kt0, i, u, 0, lds, fa, fb, acc);
+        lp2_step<Cfg, true, CHECK>(S, kt0, i, u, 0, lds, fa, fb, acc);
     }
 }
 
 // Two consecutive k-tiles i, i+1 in stages u, u+1 (u even), keeping the
 // fragments in f0 at entry and exit.
-template <class Cfg>
+template <class Cfg, bool CHECK>
 __device__ __forceinline__ void lp2_pair(const Lp2Src<Cfg> &S, int kt0, int i, int u, int nt, bool guard,
                                          uint8_t *lds, Lp2Frag<Cfg> &f0, Lp2Frag<Cfg> &f1,
                                          f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
     if (!guard || i < nt) {
-        if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg>(S, kt0, i, u, lds, f0, f1, acc);
-        else lp2_ktile<Cfg>(S, kt0, i, u, lds, f0, f1, acc);
+        if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg, CHECK>(S, kt0, i, u, lds, f0, f1, acc);
+        else lp2_ktile<Cfg, CHECK>(S, kt0, i, u, lds, f0, f1, acc);
     }
     if (!guard || i + 1 < nt) {
-        if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg>(S, kt0, i + 1, u + 1, lds, f0, f1, acc);
-        else lp2_ktile<Cfg>(S, kt0, i + 1, u + 1, lds, f1, f0, acc);
+        if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg, CHECK>(S, kt0, i + 1, u + 1, lds, f0, f1, acc);
+        else lp2_ktile<Cfg, CHECK>(S, kt0, i + 1, u + 1, lds, f1, f0, acc);
     }
 }
 
@@ -352,21 +393,32 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
         // Fill the ring with k-tiles 0 .. STAGES-1 (those past kt1 read the
         // zero chunk; they are never used).
         Lp2Src<Cfg> S;
-        lp2_sources<Cfg>(P, m0, n0, min(P.k, kt1 * Cfg::BK), S);
+        const int kend = min(P.k, kt1 * Cfg::BK);
+        lp2_sources<Cfg>(P, m0, n0, kend, lds, S);
+        // k-tiles [0, nfull) of this split lie wholly before kend
+        const int nfull = (kend - kt0 * Cfg::BK) / Cfg::BK;
 #pragma unroll
-        for (int s = 0; s < Cfg::STAGES; ++s) lp2_issue<Cfg>(S, (kt0 + s) * Cfg::BK, lds + s * Cfg::STAGE);
+        for (int s = 0; s < Cfg::STAGES; ++s) lp2_issue<Cfg>(S, (kt0 + s) * Cfg::BK, s * Cfg::STAGE);
         wait_vmcnt<(Cfg::STAGES - 1) * Cfg::LOADS>();
         __syncthreads();
         Lp2Frag<Cfg> f0, f1;
         lp2_read<Cfg>(lds, 0, f0);
         int i = 0;
+        // rounds whose refills (k-tiles i + STAGES .. i + 2 STAGES - 1) are
+        // whole: no k bound on the loads
+        for (; i + 2 * Cfg::STAGES <= nfull; i += Cfg::STAGES) {
+#pragma unroll
+            for (int u = 0; u < Cfg::STAGES; u += 2)
+                lp2_pair<Cfg, false>(S, kt0, i + u, u, nt, false, lds, f0, f1, acc);
+        }
         for (; i + Cfg::STAGES <= nt; i += Cfg::STAGES) {
 #pragma unroll
-            for (int u = 0; u < Cfg::STAGES; u += 2) lp2_pair<Cfg>(S, kt0, i + u, u, nt, false, lds, f0, f1, acc);
+            for (int u = 0; u < Cfg::STAGES; u += 2)
+                lp2_pair<Cfg, true>(S, kt0, i + u, u, nt, false, lds, f0, f1, acc);
         }
         // the last nt mod STAGES k-tiles (stages 0 ..)
 #pragma unroll
-        for (int u = 0; u < Cfg::STAGES; u += 2) lp2_pair<Cfg>(S, kt0, i + u, u, nt, true, lds, f0, f1, acc);
+        for (int u = 0; u < Cfg::STAGES; u += 2) lp2_pair<Cfg, true>(S, kt0, i + u, u, nt, true, lds, f0, f1, acc);
         wait_vmcnt<0>();   // the loads past the end have landed before the ring is reused
     }
     __syncthreads();       // the LDS ring may be refilled by this workgroup's next tile
