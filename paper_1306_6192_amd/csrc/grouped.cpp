@@ -78,8 +78,8 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan) {
         it.cost = (double)kc.bm * kc.bn * (double)std::max<int64_t>(p.k, 1);
         items.push_back(it);
     }
-    // Longest tiles first: workgroups take tiles round-robin, so each round of
-    // gridDim tiles is of similar cost.
+    // Longest tiles first: workgroups take tiles from a queue in this order,
+    // so the costliest tiles start first and the cheap ones fill the tail.
     std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
     int64_t start = 0;
     for (auto &it : items) {
@@ -137,12 +137,17 @@ static int stream_counters(hipStream_t s, int32_t **out) {
     return GEMM_OK;
 }
 
-// Pinned host staging for descriptor uploads, one per stream; an event marks
-// when the previous upload from it has finished.
+// Pinned host staging of the descriptor upload: a ring of buffers per
+// (device, stream), so that the host only waits for the copy issued
+// kRing calls earlier and can run ahead of the device by that many calls.
+// Callers on one stream take the stage's lock for the whole upload.
+static const int kRing = 4;
 struct HostStage {
-    void *host = nullptr;
-    size_t bytes = 0;
-    hipEvent_t ev = nullptr;
+    std::mutex mu;
+    void *host[kRing] = {};
+    size_t bytes[kRing] = {};
+    hipEvent_t ev[kRing] = {};
+    int next = 0;
 };
 static std::mutex g_stage_mu;
 static std::map<std::pair<int, hipStream_t>, HostStage *> g_stage;
@@ -161,18 +166,21 @@ int upload_descs(const GroupPlan &plan, hipStream_t s, const GroupDesc **dev_out
         if (!p) p = new HostStage();
         st = p;
     }
-    if (st->ev) MG_HIP(hipEventSynchronize(st->ev));
-    else MG_HIP(hipEventCreateWithFlags(&st->ev, hipEventDisableTiming));
-    if (st->bytes < bytes) {
-        if (st->host) MG_HIP(hipHostFree(st->host));
-        st->host = nullptr;
-        st->bytes = 0;
-        MG_HIP(hipHostMalloc(&st->host, std::max<size_t>(bytes, 4096), hipHostMallocDefault));
-        st->bytes = std::max<size_t>(bytes, 4096);
+    std::lock_guard<std::mutex> lk(st->mu);
+    const int b = st->next;
+    st->next = (b + 1) % kRing;
+    if (st->ev[b]) MG_HIP(hipEventSynchronize(st->ev[b]));
+    else MG_HIP(hipEventCreateWithFlags(&st->ev[b], hipEventDisableTiming));
+    if (st->bytes[b] < bytes) {
+        if (st->host[b]) MG_HIP(hipHostFree(st->host[b]));
+        st->host[b] = nullptr;
+        st->bytes[b] = 0;
+        MG_HIP(hipHostMalloc(&st->host[b], std::max<size_t>(bytes, 4096), hipHostMallocDefault));
+        st->bytes[b] = std::max<size_t>(bytes, 4096);
     }
-    memcpy(st->host, plan.descs.data(), bytes);
-    MG_HIP(hipMemcpyAsync(db->ptr, st->host, bytes, hipMemcpyHostToDevice, s));
-    MG_HIP(hipEventRecord(st->ev, s));
+    memcpy(st->host[b], plan.descs.data(), bytes);
+    MG_HIP(hipMemcpyAsync(db->ptr, st->host[b], bytes, hipMemcpyHostToDevice, s));
+    MG_HIP(hipEventRecord(st->ev[b], s));
     *dev_out = static_cast<const GroupDesc *>(db->ptr);
     return GEMM_OK;
 }

@@ -16,10 +16,11 @@
 //
 // k order: MFMA step t (0..3) of a k-tile chunk of 16 consumes k = 4g + t in
 // lane group g = l/16, so that each lane reads its four A values of the
-// chunk with one 32-byte LDS read.  Columns: lane l%16 = jj of a wave owning
-// TN = 16*CB columns reads CB consecutive B values at column CB*jj and feeds
-// value cb to accumulator block cb; block cb, lane column jj is output column
-// CB*jj + cb, and the epilogue stores CB consecutive doubles per row.
+// chunk with two 16-byte LDS reads.  Columns: lane l%16 = jj of a wave owning
+// TN = 16*CB columns feeds accumulator block cb = 2h + e with output column
+// 32h + 2jj + e (CB = 1: column jj).  Each lane thus reads, and the epilogue
+// stores, pairs of consecutive doubles, and the 16 lanes of one row read 256
+// contiguous bytes per instruction, which spreads them over all LDS banks.
 //
 // The C pointer of the TileProblem holds double elements for this tile.
 #pragma once
@@ -120,7 +121,7 @@ __device__ __forceinline__ void f64_compute_stage(const double *stage, f64x4 (&a
     const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
     const int l16 = lane & 15, g = lane >> 4;
     const double *As = stage + (wm * Cfg::TM + l16) * Cfg::SA + 4 * g;
-    const double *Bs = stage + Cfg::A_ELEMS + (4 * g) * Cfg::SB + wn * Cfg::TN + Cfg::CB * l16;
+    const double *Bs = stage + Cfg::A_ELEMS + (4 * g) * Cfg::SB + wn * Cfg::TN + (Cfg::CB == 1 ? l16 : 2 * l16);
 #pragma unroll
     for (int kc = 0; kc < Cfg::BK / 16; ++kc) {
         f64x2 af[Cfg::RB][2];
@@ -136,7 +137,7 @@ __device__ __forceinline__ void f64_compute_stage(const double *stage, f64x4 (&a
             const double *p = Bs + (kc * 16 + t) * Cfg::SB;
             if constexpr (Cfg::CB == 4) {
                 const f64x2 lo = *reinterpret_cast<const f64x2 *>(p);
-                const f64x2 hi = *reinterpret_cast<const f64x2 *>(p + 2);
+                const f64x2 hi = *reinterpret_cast<const f64x2 *>(p + 32);
                 bf[t] = f64x4{lo[0], lo[1], hi[0], hi[1]};
             } else {
                 bf[t] = *reinterpret_cast<const BVec *>(p);
@@ -166,24 +167,29 @@ __device__ __forceinline__ void f64_epilogue(double *__restrict__ C, int64_t ldc
     const int wave = threadIdx.x >> 6;
     const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
     const int l16 = lane & 15, g = lane >> 4;
-    const int col = n0 + wn * Cfg::TN + Cfg::CB * l16;
-    const bool full_cols = col + Cfg::CB <= N;
+    constexpr int PAIRS = Cfg::CB == 1 ? 1 : Cfg::CB / 2;   // column pairs per lane
+    constexpr int PW = Cfg::CB == 1 ? 1 : 2;                // doubles per pair
+    const int col0 = n0 + wn * Cfg::TN + (Cfg::CB == 1 ? l16 : 2 * l16);
 #pragma unroll
     for (int rb = 0; rb < Cfg::RB; ++rb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = m0 + wm * Cfg::TM + rb * 16 + g + 4 * r;
             if (row >= M) continue;
-            double v[Cfg::CB];
 #pragma unroll
-            for (int cb = 0; cb < Cfg::CB; ++cb) v[cb] = acc[rb][cb][r];
-            double *p = C + (int64_t)row * ldc + col;
-            if (full_cols) {
-                __builtin_memcpy(p, v, sizeof(v));
-            } else {
+            for (int h = 0; h < PAIRS; ++h) {
+                const int col = col0 + 32 * h;
+                double v[PW];
 #pragma unroll
-                for (int cb = 0; cb < Cfg::CB; ++cb)
-                    if (col + cb < N) p[cb] = v[cb];
+                for (int e = 0; e < PW; ++e) v[e] = acc[rb][PW * h + e][r];
+                double *p = C + (int64_t)row * ldc + col;
+                if (col + PW <= N) {
+                    __builtin_memcpy(p, v, sizeof(v));
+                } else {
+#pragma unroll
+                    for (int e = 0; e < PW; ++e)
+                        if (col + e < N) p[e] = v[e];
+                }
             }
         }
     }

@@ -16,7 +16,7 @@
 //     lane 4r + c addressing B[k0+r][n0+4c..] yields B[k0..k0+3][n0+j] in
 //     lane j (b8: lane 2r + c addressing B[k0+r][n0+8c..]).
 //   * Rows are XOR-swizzled at 16-byte granularity so that the fragment reads
-//     of 8 (A) or 4-8 (B) consecutive rows hit distinct LDS banks; the
+//     of 16 (A) or 4-8 (B) consecutive rows hit distinct LDS banks; the
 //     swizzle is applied on the global side of the direct loads (each lane
 //     picks which logical chunk it fetches), since the LDS side is fixed.
 // Shape requirements (checked on the host; other shapes use tile_lp.hpp):
@@ -74,7 +74,11 @@ struct Lp2Cfg {
     static_assert(STAGES >= 2 && (STAGES - 1) * LOADS < 64, "vmcnt range");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
     // physical chunk of logical chunk c in A row r / B row k
-    __device__ static __forceinline__ int a_swz(int r) { return (r >> 1) & 3; }
+    // A rows are 64 bytes (4 chunks); a fragment read of 16 consecutive rows
+    // (one 16-lane phase of a 16-byte LDS read on the 64 banks) touches 4
+    // rows of each (r mod 4) class: XOR-ing the chunk with bits 1-2 of the row
+    // gives those 16 rows distinct banks (and 8 consecutive rows too).
+    __device__ static __forceinline__ int a_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
     __device__ static __forceinline__ int b_swz(int k) {
         return (ESZ == 2 ? 4 * (k & 3) : 2 * (k & 7)) & (B_CPR - 1);
     }
