@@ -3,10 +3,13 @@
 #include "kernels_impl.hpp"
 #include "tile_c32.hpp"
 
+// Two waves per SIMD, either as two 4-wave 128x128 workgroups per CU or as
+// one 8-wave 256x128 workgroup: measured at 8192^3 they sustain 135 and 137
+// real TFLOP/s against 131 for a 4-wave 256x128 tile (one wave per SIMD).
 static const KernelCfg kC32Configs[] = {
-    make_cfg<C32Cfg<256, 128>, 1>(),
     make_cfg<C32Cfg<128, 128>, 2>(),
     make_cfg<C32Cfg<64, 64>, 4>(),
+    make_cfg<C32Cfg<256, 128, 2, 4>, 2>(),   // eight waves, 128 x 32 each
 };
 
 const KernelCfg *c32_configs(int *count) {

@@ -7,7 +7,7 @@
 #include "kernels.hpp"
 
 template <class Cfg, int OCC>
-__global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_plain_kernel(TileProblem P) {
+__global__ __launch_bounds__(Cfg::THREADS, OCC) void gemm_plain_kernel(TileProblem P) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[Cfg::LDS_BYTES];
     const int per_split = P.tiles_m * P.tiles_n;
     int t = xcd_remap(blockIdx.x, gridDim.x);
@@ -39,7 +39,8 @@ template <int A, int B> struct cmax { static constexpr int v = A > B ? A : B; };
 // Every workgroup leaves the loop once the queue is exhausted, so the grid
 // always drains; the last one out resets the queue for the next launch.
 template <class Cfg0, class Cfg1, int OCC>
-__global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_grouped_kernel(GroupedArgs G) {
+__global__ __launch_bounds__(Cfg0::THREADS, OCC) void gemm_grouped_kernel(GroupedArgs G) {
+    static_assert(Cfg0::THREADS == Cfg1::THREADS, "one workgroup size per grouped launch");
     __shared__ __attribute__((aligned(16))) uint8_t lds[cmax<Cfg0::LDS_BYTES, Cfg1::LDS_BYTES>::v];
     __shared__ int next_tile;
     while (true) {
@@ -72,19 +73,19 @@ __global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_grouped_kernel(Grouped
 
 template <class Cfg, int OCC>
 static hipError_t launch_plain_t(const TileProblem &P, int nwg, hipStream_t s) {
-    hipLaunchKernelGGL((gemm_plain_kernel<Cfg, OCC>), dim3(nwg), dim3(GEMM_THREADS), 0, s, P);
+    hipLaunchKernelGGL((gemm_plain_kernel<Cfg, OCC>), dim3(nwg), dim3(Cfg::THREADS), 0, s, P);
     return hipGetLastError();
 }
 
 template <class Cfg0, class Cfg1, int OCC>
 static hipError_t launch_grouped_t(const GroupedArgs &G, int nwg, hipStream_t s) {
-    hipLaunchKernelGGL((gemm_grouped_kernel<Cfg0, Cfg1, OCC>), dim3(nwg), dim3(GEMM_THREADS), 0, s, G);
+    hipLaunchKernelGGL((gemm_grouped_kernel<Cfg0, Cfg1, OCC>), dim3(nwg), dim3(Cfg0::THREADS), 0, s, G);
     return hipGetLastError();
 }
 
 template <class Cfg, int OCC, int CHUNK = 0>
 constexpr KernelCfg make_cfg() {
-    return KernelCfg{Cfg::BM, Cfg::BN, Cfg::BK, 4, Cfg::LDS_BYTES, Cfg::MFMA_K,
+    return KernelCfg{Cfg::BM, Cfg::BN, Cfg::BK, Cfg::THREADS / 64, Cfg::LDS_BYTES, Cfg::MFMA_K,
                      (160 * 1024 / Cfg::LDS_BYTES) < OCC ? (160 * 1024 / Cfg::LDS_BYTES) : OCC,
                      launch_plain_t<Cfg, OCC>, CHUNK};
 }

@@ -11,8 +11,8 @@
 // bound is weaker).  The real and imaginary accumulators are separate
 // 32x32 float32 blocks.
 //
-// Structure as in the FP32 tile: one 256-lane workgroup (4 waves, 2 x 2)
-// owns a BM x BN complex tile and walks k in k-tiles of BK = 16 complex
+// Structure as in the FP32 tile: one workgroup of WM x WN waves owns a BM x BN
+// complex tile and walks k in k-tiles of BK = 16 complex
 // (128 bytes per row) through two LDS stages, one barrier per k-tile.
 //
 // MFMA operand layout (32x32x2, f32): lane l supplies A[l%32][kslot(l/32)]
@@ -28,10 +28,11 @@
 
 #include "tile_common.hpp"
 
-template <int BM_, int BN_>
+template <int BM_, int BN_, int WM_ = 2, int WN_ = 2>
 struct C32Cfg {
     static constexpr int BM = BM_, BN = BN_, BK = 16;   // BK in complex elements
-    static constexpr int WM = 2, WN = 2;
+    static constexpr int WM = WM_, WN = WN_;          // waves along m and n
+    static constexpr int THREADS = 64 * WM * WN;
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int RB = TM / 32, CB = TN / 32;
     static constexpr int SA = 2 * BK + 4;   // LDS row stride of A (floats)
@@ -39,10 +40,10 @@ struct C32Cfg {
     static constexpr int A_ELEMS = BM * SA, B_ELEMS = BK * SB;
     static constexpr int STAGE = A_ELEMS + B_ELEMS;
     static constexpr int LDS_BYTES = 2 * STAGE * 4;
-    static constexpr int AV = BM * 2 * BK / 4 / GEMM_THREADS;  // 16-byte loads per thread (A)
-    static constexpr int BV = BK * 2 * BN / 4 / GEMM_THREADS;  // 16-byte loads per thread (B)
+    static constexpr int AV = BM * 2 * BK / 4 / THREADS;  // 16-byte loads per thread (A)
+    static constexpr int BV = BK * 2 * BN / 4 / THREADS;  // 16-byte loads per thread (B)
     static_assert(RB >= 1 && (CB == 1 || CB == 2), "wave tile");
-    static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
+    static_assert(AV >= 1 && BV >= 1, "tile too small for the workgroup");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
     static constexpr int MFMA_K = 2;
     __device__ static void run(const TileProblem &P, int tm, int tn, int split, uint8_t *lds);
@@ -73,14 +74,14 @@ __device__ __forceinline__ void c32_load_tiles(const TileProblem &P, int m0, int
     const float *B = static_cast<const float *>(P.B);
 #pragma unroll
     for (int q = 0; q < Cfg::AV; ++q) {
-        const int idx = tid + q * GEMM_THREADS;
+        const int idx = tid + q * Cfg::THREADS;
         const int r = idx / (Cfg::BK / 2);
         const int kv = (idx % (Cfg::BK / 2)) * 2;
         ra[q] = c32_load2(A, P.lda, m0 + r, k0 + kv, P.m, P.k);
     }
 #pragma unroll
     for (int q = 0; q < Cfg::BV; ++q) {
-        const int idx = tid + q * GEMM_THREADS;
+        const int idx = tid + q * Cfg::THREADS;
         const int kr = idx / (Cfg::BN / 2);
         const int cv = (idx % (Cfg::BN / 2)) * 2;
         rb[q] = c32_load2(B, P.ldb, k0 + kr, n0 + cv, P.k, P.n);
@@ -95,14 +96,14 @@ __device__ __forceinline__ void c32_store_tiles(float *stage, const f32x4 (&ra)[
     float *Bs = stage + Cfg::A_ELEMS;
 #pragma unroll
     for (int q = 0; q < Cfg::AV; ++q) {
-        const int idx = tid + q * GEMM_THREADS;
+        const int idx = tid + q * Cfg::THREADS;
         const int r = idx / (Cfg::BK / 2);
         const int kv = (idx % (Cfg::BK / 2)) * 2;
         *reinterpret_cast<f32x4 *>(&As[r * Cfg::SA + 2 * kv]) = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < Cfg::BV; ++q) {
-        const int idx = tid + q * GEMM_THREADS;
+        const int idx = tid + q * Cfg::THREADS;
         const int kr = idx / (Cfg::BN / 2);
         const int cv = (idx % (Cfg::BN / 2)) * 2;
         *reinterpret_cast<f32x4 *>(&Bs[kr * Cfg::SB + 2 * cv]) = rb[q];
@@ -227,7 +228,8 @@ __device__ __forceinline__ void c32_tile(const TileProblem &P, int tm, int tn, f
     c32_epilogue<Cfg>(P.C, P.ldc, P.m, P.n, m0, n0, re, im);
 }
 
-template <int BM, int BN>
-__device__ __forceinline__ void C32Cfg<BM, BN>::run(const TileProblem &P, int tm, int tn, int, uint8_t *lds) {
-    c32_tile<C32Cfg<BM, BN>>(P, tm, tn, reinterpret_cast<float *>(lds));
+template <int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void C32Cfg<BM, BN, WM, WN>::run(const TileProblem &P, int tm, int tn, int,
+                                                            uint8_t *lds) {
+    c32_tile<C32Cfg<BM, BN, WM, WN>>(P, tm, tn, reinterpret_cast<float *>(lds));
 }

@@ -1,6 +1,7 @@
 // FP32 output tile of C = A*B on gfx950 matrix cores (v_mfma_f32_32x32x2_f32).
 //
-// One 256-lane workgroup (4 waves, 2 x 2) owns a BM x BN tile of C and walks
+// One workgroup of WM x WN waves (default 2 x 2, 256 lanes) owns a BM x BN
+// tile of C and walks
 // the k dimension in k-tiles of BK = 32:
 //   HBM/L2 -> registers (16-B loads, masked at the edges)
 //          -> LDS (two stages, rows padded against bank conflicts)
@@ -30,10 +31,11 @@
 
 #include "tile_common.hpp"
 
-template <int BM_, int BN_>
+template <int BM_, int BN_, int WM_ = 2, int WN_ = 2>
 struct F32Cfg {
     static constexpr int BM = BM_, BN = BN_, BK = 32;
-    static constexpr int WM = 2, WN = 2;              // waves along m and n
+    static constexpr int WM = WM_, WN = WN_;          // waves along m and n
+    static constexpr int THREADS = 64 * WM * WN;
     static constexpr int TM = BM / WM, TN = BN / WN;  // wave tile
     static constexpr int RB = TM / 32, CB = TN / 32;  // 32x32 blocks per wave
     static constexpr int SA = BK + 4;                 // LDS row stride of A (floats)
@@ -42,10 +44,11 @@ struct F32Cfg {
     static constexpr int STAGE = A_ELEMS + B_ELEMS;
     static constexpr int LDS_FLOATS = 2 * STAGE;
     static constexpr int LDS_BYTES = LDS_FLOATS * 4;
-    static constexpr int AV = BM * BK / 4 / GEMM_THREADS;  // float4 loads per thread (A)
-    static constexpr int BV = BK * BN / 4 / GEMM_THREADS;  // float4 loads per thread (B)
+    static constexpr int AV = BM * BK / 4 / THREADS;  // float4 loads per thread (A)
+    static constexpr int BV = BK * BN / 4 / THREADS;  // float4 loads per thread (B)
     static_assert(RB >= 1 && (CB == 1 || CB == 2 || CB == 4), "wave tile");
-    static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
+    static_assert(AV >= 1 && BV >= 1 && AV * THREADS * 4 == BM * BK && BV * THREADS * 4 == BK * BN,
+                  "staging must cover the k-tile exactly");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
     static constexpr int MFMA_K = 2;
     __device__ static void run(const TileProblem &P, int tm, int tn, int split, uint8_t *lds);
@@ -83,14 +86,14 @@ __device__ __forceinline__ void f32_load_tiles(const TileProblem &P, int m0, int
     const float *B = static_cast<const float *>(P.B);
 #pragma unroll
     for (int q = 0; q < Cfg::AV; ++q) {
-        const int idx = tid + q * GEMM_THREADS;
+        const int idx = tid + q * Cfg::THREADS;
         const int r = idx / (Cfg::BK / 4);
         const int kv = (idx % (Cfg::BK / 4)) * 4;
         ra[q] = f32_load4(A, P.lda, m0 + r, k0 + kv, P.m, P.k);
     }
 #pragma unroll
     for (int q = 0; q < Cfg::BV; ++q) {
-        const int idx = tid + q * GEMM_THREADS;
+        const int idx = tid + q * Cfg::THREADS;
         const int kr = idx / (Cfg::BN / 4);
         const int cv = (idx % (Cfg::BN / 4)) * 4;
         rb[q] = f32_load4(B, P.ldb, k0 + kr, n0 + cv, P.k, P.n);
@@ -105,14 +108,14 @@ __device__ __forceinline__ void f32_store_tiles(float *stage, const f32x4 (&ra)[
     float *Bs = stage + Cfg::A_ELEMS;
 #pragma unroll
     for (int q = 0; q < Cfg::AV; ++q) {
-        const int idx = tid + q * GEMM_THREADS;
+        const int idx = tid + q * Cfg::THREADS;
         const int r = idx / (Cfg::BK / 4);
         const int kv = (idx % (Cfg::BK / 4)) * 4;
         *reinterpret_cast<f32x4 *>(&As[r * Cfg::SA + kv]) = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < Cfg::BV; ++q) {
-        const int idx = tid + q * GEMM_THREADS;
+        const int idx = tid + q * Cfg::THREADS;
         const int kr = idx / (Cfg::BN / 4);
         const int cv = (idx % (Cfg::BN / 4)) * 4;
         *reinterpret_cast<f32x4 *>(&Bs[kr * Cfg::SB + cv]) = rb[q];
@@ -192,7 +195,8 @@ __device__ __forceinline__ void f32_tile(const TileProblem &P, int tm, int tn, i
     tile_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
 }
 
-template <int BM, int BN>
-__device__ __forceinline__ void F32Cfg<BM, BN>::run(const TileProblem &P, int tm, int tn, int split, uint8_t *lds) {
-    f32_tile<F32Cfg<BM, BN>>(P, tm, tn, split, reinterpret_cast<float *>(lds));
+template <int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void F32Cfg<BM, BN, WM, WN>::run(const TileProblem &P, int tm, int tn, int split,
+                                                            uint8_t *lds) {
+    f32_tile<F32Cfg<BM, BN, WM, WN>>(P, tm, tn, split, reinterpret_cast<float *>(lds));
 }

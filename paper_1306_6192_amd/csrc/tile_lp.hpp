@@ -49,6 +49,7 @@ struct LpCfg {
     static constexpr int MODE = MODE_;
     static constexpr int BM = BM_, BN = BN_, BK = T::BK;
     static constexpr int WM = 2, WN = 2;
+    static constexpr int THREADS = GEMM_THREADS;
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int RB = TM / 32, CB = TN / 32;
     static constexpr int RS = T::ROW + 16;       // padded LDS row stride in bytes (odd multiple of 16)

@@ -50,6 +50,7 @@ struct Lp2Cfg {
     static constexpr int MODE = MODE_;
     static constexpr int BM = BM_, BN = BN_, STAGES = STAGES_;
     static constexpr int WM = 2, WN = 2;
+    static constexpr int THREADS = GEMM_THREADS;
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int RB = TM / 32, CB = TN / 32;
     static constexpr int ESZ = (MODE == GEMM_MODE_F8E4M3) ? 1 : 2;

@@ -105,9 +105,9 @@ def test_config_tables():
     for c in range(n):
         assert lib.gemm_config_info(0, c, info) == 0
         bm, bn, bk, waves, lds, mk = list(info)
-        assert bm % 32 == 0 and bn % 32 == 0 and bk == 32 and waves == 4 and 0 < lds <= 160 * 1024
-        seen.add((bm, bn))
-    assert len(seen) == n
+        assert bm % 32 == 0 and bn % 32 == 0 and bk == 32 and waves in (4, 8) and 0 < lds <= 160 * 1024
+        seen.add((bm, bn, waves))
+    assert len(seen) >= n - 1   # the two 8-wave 256x256 tiles differ only in their wave grid
     assert lib.gemm_config_info(0, n, info) == _lib.GEMM_EINVAL
     assert lib.gemm_num_configs(9) == _lib.GEMM_EINVAL
 
@@ -201,7 +201,7 @@ def test_f64_c32_config_tables():
         assert n >= 2
         for c in range(n):
             assert lib.gemm_config_info(mode, c, info) == 0
-            assert info[2] == 16 and info[3] == 4 and info[5] == mk and 0 < info[4] <= 160 * 1024
+            assert info[2] == 16 and info[3] in (4, 8) and info[5] == mk and 0 < info[4] <= 160 * 1024
     assert lib.gemm_num_configs(_lib.NUM_KERNEL_FAMILIES) == _lib.GEMM_EINVAL
     c, s = ctypes.c_int32(), ctypes.c_int32()
     assert lib.gemm_tuner_lookup(_lib.MODE_F64, 4096, 4096, 4096, ctypes.byref(c), ctypes.byref(s)) == \
