@@ -184,14 +184,16 @@ def section_plain(args, torch, mg, synth, stream, line):
                           "cfg": mg.config_info(mg.MODE_F32, cfg), "split_k": split,
                           "rel_err_sampled": float(oracle.relerr(C[rows, cols], R))})
         if (m, n, k) == DOMINANT:
-            dom = (avg, tf)
+            info = mg.config_info(mg.MODE_F32, cfg)
+            dom = (avg, tf, f"gemm_plain_kernel, FP32 {info['BM']}x{info['BN']} tile, {info['waves']} waves "
+                            f"(config {cfg}), 8192^3")
     line.update({
         "value": round(value, 3),
         "ms_per_step": round(total_ms / args.steps, 4),
         "roofline": {"bound": "mfma", "achieved": round(dom[1], 3), "peak": PEAK["f32"], "unit": "TFLOP/s",
                      "frac": round(dom[1] / PEAK["f32"], 4),
-                     "traffic": measured_traffic("gemm_plain_kernel<F32Cfg<256,256>> 8192^3"),
-                     "kernel": "gemm_plain_kernel<F32Cfg<256,256>>, 8192^3", "avg_launch_ms": round(dom[0], 4)},
+                     "traffic": measured_traffic(dom[2]),
+                     "kernel": dom[2], "avg_launch_ms": round(dom[0], 4)},
         "per_shape": per_shape,
         "max_rel_err_sampled": max(p["rel_err_sampled"] for p in per_shape),
         "wall_s_timed": round(wall, 3),

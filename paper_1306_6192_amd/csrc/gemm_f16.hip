@@ -14,6 +14,8 @@ static const KernelCfg kTable[] = {
     make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 4>, 1, 8>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 128, 4>, 1, 8>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F16, 128, 256, 4>, 1, 8>(), make_cfg<Lp2Cfg<GEMM_MODE_F16, 128, 128, 4>, 2, 8>(),
+    // eight waves (two per SIMD): 2 x 4 (128 x 64 each) and 4 x 2 (64 x 128 each)
+    make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 4, 2, 4>, 2, 8>(), make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 4, 4, 2>, 2, 8>(),
 };
 
 const KernelCfg *lp_configs_f16(int *count) {

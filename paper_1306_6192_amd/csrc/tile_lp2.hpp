@@ -45,12 +45,13 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <int MODE_, int BM_, int BN_, int STAGES_>
+template <int MODE_, int BM_, int BN_, int STAGES_, int WM_ = 2, int WN_ = 2>
 struct Lp2Cfg {
     static constexpr int MODE = MODE_;
     static constexpr int BM = BM_, BN = BN_, STAGES = STAGES_;
-    static constexpr int WM = 2, WN = 2;
-    static constexpr int THREADS = GEMM_THREADS;
+    static constexpr int WM = WM_, WN = WN_;            // waves along m and n
+    static constexpr int WAVES = WM * WN;
+    static constexpr int THREADS = 64 * WAVES;
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int RB = TM / 32, CB = TN / 32;
     static constexpr int ESZ = (MODE == GEMM_MODE_F8E4M3) ? 1 : 2;
@@ -66,12 +67,13 @@ struct Lp2Cfg {
     static constexpr int B_STAGE = BK * B_ROWB;
     static constexpr int STAGE = A_STAGE + B_STAGE;
     static constexpr int LDS_BYTES = STAGES * STAGE;
-    static constexpr int A_LOADS = A_STAGE / 1024 / 4;  // direct loads per wave per k-tile
-    static constexpr int B_LOADS = B_STAGE / 1024 / 4;
+    static constexpr int A_LOADS = A_STAGE / 1024 / WAVES;  // direct loads per wave per k-tile
+    static constexpr int B_LOADS = B_STAGE / 1024 / WAVES;
     static constexpr int LOADS = A_LOADS + B_LOADS;
     static_assert(RB >= 1 && CB >= 1, "wave tile");
-    static_assert(A_LOADS >= 1 && B_LOADS >= 1 && A_LOADS * 4096 == A_STAGE && B_LOADS * 4096 == B_STAGE,
-                  "stage sizes must be whole numbers of 4 x 1 KiB loads");
+    static_assert(A_LOADS >= 1 && B_LOADS >= 1 && A_LOADS * 1024 * WAVES == A_STAGE &&
+                      B_LOADS * 1024 * WAVES == B_STAGE,
+                  "stage sizes must be whole numbers of one 1 KiB load per wave");
     static_assert(STAGES >= 2 && (STAGES - 1) * LOADS < 64, "vmcnt range");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
     // physical chunk of logical chunk c in A row r / B row k
@@ -434,8 +436,8 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
     lp2_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
 }
 
-template <int MODE, int BM, int BN, int STAGES>
-__device__ __forceinline__ void Lp2Cfg<MODE, BM, BN, STAGES>::run(const TileProblem &P, int tm, int tn, int split,
-                                                                   uint8_t *lds) {
-    lp2_tile<Lp2Cfg<MODE, BM, BN, STAGES>>(P, tm, tn, split, lds);
+template <int MODE, int BM, int BN, int STAGES, int WM, int WN>
+__device__ __forceinline__ void Lp2Cfg<MODE, BM, BN, STAGES, WM, WN>::run(const TileProblem &P, int tm, int tn,
+                                                                           int split, uint8_t *lds) {
+    lp2_tile<Lp2Cfg<MODE, BM, BN, STAGES, WM, WN>>(P, tm, tn, split, lds);
 }
