@@ -14,7 +14,8 @@ from ._lib import (GEMM_EBUSY, GEMM_EINVAL, GEMM_ENOMEM, GEMM_EUNSUPPORTED, GEMM
                    MODE_BF16, MODE_C32, MODE_F8E4M3, MODE_F16, MODE_F32, MODE_F64, MODE_NAMES, MODE_SPLIT_BF16X3,
                    GemmError, check, load)
 
-__all__ = ["gemm", "gemm_f64", "gemm_c32", "add", "convert", "quantize_e4m3", "errnorm", "grouped", "GroupedGraph", "Server", "tune",
+__all__ = ["gemm", "gemm_f64", "gemm_c32", "add", "convert", "quantize_e4m3", "errnorm", "grouped", "ProblemBatch",
+           "GroupedGraph", "Server", "tune",
            "tuner_lookup", "config_info", "num_configs", "GemmError", "MODE_F32", "MODE_BF16", "MODE_F16",
            "MODE_F8E4M3", "MODE_SPLIT_BF16X3", "MODE_F64", "MODE_C32", "MODE_NAMES", "load"]
 
@@ -228,10 +229,25 @@ def tune(mode, m, n, k, stream=None):
 def grouped(problems, mode=MODE_F32, stream=None):
     """Run many products in one persistent launch.  ``problems`` is a list of
     (A, B, C) device tensors (all of one mode); FP8 entries may be
-    (A, B, C, scale_a, scale_b)."""
-    probs = [make_problem(t[0], t[1], t[2], mode, *(t[3:5] if len(t) >= 5 else (1.0, 1.0))) for t in problems]
-    arr = _lib.problems_array(probs)
-    check(load().gemm_grouped(arr, len(probs), _stream_ptr(stream)))
+    (A, B, C, scale_a, scale_b), or a :class:`ProblemBatch` built once."""
+    batch = problems if isinstance(problems, ProblemBatch) else ProblemBatch(problems, mode)
+    batch.run(stream)
+
+
+class ProblemBatch:
+    """A list of (A, B, C) device tensors turned once into the C-ABI problem
+    array, so that repeated grouped launches of the same problems pay no
+    per-problem Python cost (the tensors are kept alive with it)."""
+
+    def __init__(self, problems, mode=MODE_F32):
+        probs = [make_problem(t[0], t[1], t[2], mode, *(t[3:5] if len(t) >= 5 else (1.0, 1.0)))
+                 for t in problems]
+        self._keep = problems
+        self.count = len(probs)
+        self.array = _lib.problems_array(probs)
+
+    def run(self, stream=None):
+        check(load().gemm_grouped(self.array, self.count, _stream_ptr(stream)))
 
 
 class GroupedGraph:

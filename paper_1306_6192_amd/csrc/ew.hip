@@ -6,6 +6,9 @@
 // Launch shape: blockIdx.y walks rows (grid-stride), blockIdx.x covers a
 // row in spans of 256 threads x 4 chunks of 16 bytes; each thread issues its
 // eight loads before any arithmetic so that they are all in flight at once.
+// The double form streams with non-temporal loads and stores (measured at
+// 4096^2: 6.5 TB/s against 5.7 with ordinary ones; for float the ordinary
+// ones are faster, 6.9 against 6.3 TB/s).
 // C may be A or B itself (same stride): every element is read by the thread
 // that writes it, before the write.
 #include "kernels.hpp"
@@ -27,8 +30,15 @@ __global__ __launch_bounds__(256) void ew_add_kernel(const T *A, int64_t lda, co
         for (int u = 0; u < EW_UNROLL; ++u) {
             const int64_t col = (ch0 + u * 256) * V;
             if (col + V <= n) {
-                __builtin_memcpy(va[u], a + col, 16);
-                __builtin_memcpy(vb[u], b + col, 16);
+                if constexpr (sizeof(T) == 8) {
+                    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a + col));
+                    const u32x4 y = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(b + col));
+                    __builtin_memcpy(va[u], &x, 16);
+                    __builtin_memcpy(vb[u], &y, 16);
+                } else {
+                    __builtin_memcpy(va[u], a + col, 16);
+                    __builtin_memcpy(vb[u], b + col, 16);
+                }
             } else {
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
@@ -44,7 +54,13 @@ __global__ __launch_bounds__(256) void ew_add_kernel(const T *A, int64_t lda, co
 #pragma unroll
             for (int e = 0; e < V; ++e) vc[e] = subtract ? va[u][e] - vb[u][e] : va[u][e] + vb[u][e];
             if (col + V <= n) {
-                __builtin_memcpy(c + col, vc, 16);
+                if constexpr (sizeof(T) == 8) {
+                    u32x4 z;
+                    __builtin_memcpy(&z, vc, 16);
+                    __builtin_nontemporal_store(z, reinterpret_cast<u32x4 *>(c + col));
+                } else {
+                    __builtin_memcpy(c + col, vc, 16);
+                }
             } else {
 #pragma unroll
                 for (int e = 0; e < V; ++e)
