@@ -156,6 +156,7 @@ Launch make_launch(const gemm_problem_t &p, const KernelCfg &kc, int split) {
 }
 
 bool cfg_eligible(const gemm_problem_t &p, const KernelCfg &kc) {
+    if (kc.presplit) return p.n % 8 == 0 && p.n >= 8;
     if (kc.chunk == 0) return true;
     const int64_t c = kc.chunk;
     return p.k % c == 0 && p.n % c == 0 && p.n >= c && p.lda % c == 0 && p.ldb % c == 0 &&
@@ -167,15 +168,30 @@ int effective_cfg(const gemm_problem_t &p, int cfg) {
     const KernelCfg *t = configs(p.mode, &count);
     if (!t || cfg < 0 || cfg >= count || cfg_eligible(p, t[cfg])) return cfg;
     for (int c = 0; c < count; ++c)
-        if (t[c].chunk == 0 && t[c].bm == t[cfg].bm && t[c].bn == t[cfg].bn) return c;
+        if (t[c].chunk == 0 && !t[c].presplit && t[c].bm == t[cfg].bm && t[c].bn == t[cfg].bn) return c;
     return 0;
+}
+
+// Bytes of the interleaved operand copies of the pre-split path (A' then B',
+// each 256-byte aligned).
+static int64_t presplit_bytes(const gemm_problem_t &p, int64_t *b_off) {
+    const int64_t k16 = (p.k + 15) / 16 * 16;
+    const int64_t a = ((int64_t)p.m * 3 * k16 * 2 + 255) / 256 * 256;
+    *b_off = a;
+    return a + ((int64_t)3 * k16 * p.n * 2 + 255) / 256 * 256;
 }
 
 int64_t plain_ws_bytes(const gemm_problem_t &p, int cfg, int split) {
     int count = 0;
     const KernelCfg *t = configs(p.mode, &count);
     if (!t || cfg < 0 || cfg >= count || p.m == 0 || p.n == 0 || p.k == 0) return 0;
-    return make_launch(p, t[effective_cfg(p, cfg)], split).ws_bytes;
+    const KernelCfg &kc = t[effective_cfg(p, cfg)];
+    int64_t ws = (make_launch(p, kc, split).ws_bytes + 255) / 256 * 256;
+    if (kc.presplit) {
+        int64_t b_off = 0;
+        ws += presplit_bytes(p, &b_off);
+    }
+    return ws;
 }
 
 int enqueue_plain(const gemm_problem_t &p, int cfg, int split, void *ws, hipStream_t s) {
@@ -193,6 +209,26 @@ int enqueue_plain(const gemm_problem_t &p, int cfg, int split, void *ws, hipStre
     if (L.splits > 1) {
         if (!ws) return fail(GEMM_EINTERNAL, "split-K workspace missing");
         L.P.C = static_cast<float *>(ws);
+    }
+    if (t[cfg].presplit) {
+        // interleaved bfloat16 operands after the split-K slabs; the product
+        // runs over 3 k16 with three BF16 k-tiles per 32-k split grain
+        if (!ws) return fail(GEMM_EINTERNAL, "pre-split workspace missing");
+        int64_t b_off = 0;
+        presplit_bytes(p, &b_off);
+        uint8_t *base = static_cast<uint8_t *>(ws) + (L.ws_bytes + 255) / 256 * 256;
+        uint16_t *Ap = reinterpret_cast<uint16_t *>(base);
+        uint16_t *Bp = reinterpret_cast<uint16_t *>(base + b_off);
+        const int64_t k16 = (p.k + 15) / 16 * 16;
+        MG_HIP(launch_presplit(static_cast<const float *>(p.A), p.lda, static_cast<const float *>(p.B), p.ldb,
+                               (int)p.m, (int)p.n, (int)p.k, Ap, Bp, s));
+        L.P.A = Ap;
+        L.P.B = Bp;
+        L.P.lda = 3 * k16;
+        L.P.ldb = p.n;
+        L.P.k = (int32_t)(3 * k16);
+        L.P.kt_per_split = L.P.kt_per_split * 3;
+        L.P.vec = 3;
     }
     MG_HIP(t[cfg].plain(L.P, L.nwg, s));
     if (L.splits > 1)

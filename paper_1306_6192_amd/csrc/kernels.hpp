@@ -32,6 +32,11 @@ struct KernelCfg {
     // (`chunk` elements): k, n, lda and ldb must be multiples of it and A, B
     // 16-byte aligned.
     int chunk;
+    // split-BF16x3 only: the float32 operands are first split into an
+    // interleaved bfloat16 copy (A' = [lo hi hi], B' = [hi; lo; hi] per 16 k)
+    // and the product runs as one BF16 product over 3 x k16 (`plain` is then
+    // a BF16 kernel).  Needs n a multiple of 8; any k, strides, alignment.
+    int presplit;
 };
 
 // The grouped kernel of a mode: two tile configurations (indices into the
@@ -64,5 +69,11 @@ hipError_t launch_quantize_e4m3(const float *x, int64_t count, uint8_t *q, float
 hipError_t launch_ew_add(int elem_bytes, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                          int64_t ldc, int m, int n, int subtract, hipStream_t s);
 hipError_t launch_zero_rows(void *C, int64_t ld_bytes, int m, int64_t row_bytes, hipStream_t s);
+// The interleaved bfloat16 operands of the pre-split split-BF16x3 path
+// (presplit.hip): A (m x k float32, lda) -> Ap (m x 3 k16, row stride 3 k16);
+// B (k x n float32, ldb) -> Bp (3 k16 x n, row stride n); k16 = k rounded up
+// to 16, the padding zero.
+hipError_t launch_presplit(const float *A, int64_t lda, const float *B, int64_t ldb, int m, int n, int k,
+                           uint16_t *Ap, uint16_t *Bp, hipStream_t s);
 hipError_t launch_errnorm(const float *C, int64_t ldc, const double *R, int64_t ldr, int64_t m,
                           int64_t n, double *out3, double *partials, int nparts, hipStream_t s);

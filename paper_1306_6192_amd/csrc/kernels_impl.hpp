@@ -83,9 +83,9 @@ static hipError_t launch_grouped_t(const GroupedArgs &G, int nwg, hipStream_t s)
     return hipGetLastError();
 }
 
-template <class Cfg, int OCC, int CHUNK = 0>
+template <class Cfg, int OCC, int CHUNK = 0, int PRESPLIT = 0>
 constexpr KernelCfg make_cfg() {
     return KernelCfg{Cfg::BM, Cfg::BN, Cfg::BK, Cfg::THREADS / 64, Cfg::LDS_BYTES, Cfg::MFMA_K,
                      (160 * 1024 / Cfg::LDS_BYTES) < OCC ? (160 * 1024 / Cfg::LDS_BYTES) : OCC,
-                     launch_plain_t<Cfg, OCC>, CHUNK};
+                     launch_plain_t<Cfg, OCC>, CHUNK, PRESPLIT};
 }
