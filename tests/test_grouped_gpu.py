@@ -127,3 +127,20 @@ def test_grouped_edge_cases():
     assert "mode" in _lib.last_error()
     h = ctypes.c_void_p()
     assert lib.gemm_grouped_graph_create(arr, 2, ctypes.byref(h)) == _lib.GEMM_EINVAL
+
+
+def test_problem_batch_repeated_launches():
+    """A ProblemBatch (problem array built once) launched repeatedly on one
+    stream -- the descriptor uploads cycle through the pinned staging ring --
+    gives the list form's bits every time."""
+    log("grouped problem batch x6")
+    probs, ops = _group(48, 32, 300, 7, mg.MODE_F32)
+    mg.grouped(ops)
+    want = [host(c).copy() for _, _, c in ops]
+    batch = mg.ProblemBatch(ops)
+    for rep in range(6):
+        for _, _, c in ops:
+            c.fill_(float("nan"))
+        batch.run()
+        for i, (_, _, c) in enumerate(ops):
+            assert np.array_equal(host(c), want[i]), (rep, i)

@@ -179,6 +179,31 @@ def test_cross_config_bitwise_and_identity(mode):
     assert np.array_equal(host(mg.gemm(xa, ia, mode=mode)), X)
 
 
+@pytest.mark.parametrize("m,n,k", [(97, 64, 333), (1, 8, 1), (257, 136, 47), (64, 520, 4100)])
+def test_split_presplit_matches_register_staged(m, n, k):
+    """The pre-split split-BF16x3 path (interleaved operand copies, one BF16
+    product over 3 k16) gives the register-staged split tile's bits, for k
+    not a multiple of 16 and for strided, misaligned float32 operands."""
+    log(f"precision split pre-split {(m, n, k)}")
+    mode = mg.MODE_SPLIT_BF16X3
+    A, B = synth.pair(m, n, k, seed=34, dist="normal")
+    bufA = torch.zeros((m, k + 5), dtype=torch.float32, device="cuda")
+    bufB = torch.zeros((k, n + 8), dtype=torch.float32, device="cuda")
+    bufA[:, 1:k + 1] = dev(A)
+    bufB[:, 3:n + 3] = dev(B)
+    a, b = bufA[:, 1:k + 1], bufB[:, 3:n + 3]
+    # the table lists the register-staged tiles first, then the pre-split ones
+    pre = list(range(6, mg.num_configs(mode)))
+    assert pre, "no pre-split configurations"
+    R, W, terms, extra = secondary(A, B, mode)
+    for split in (1, 2):
+        ref = host(mg.gemm(a, b, mode=mode, cfg=2, split_k=split))
+        check_bound(ref, R, W, terms, f"split register-staged {(m, n, k)} split {split}", extra)
+        for cfg in pre:
+            got = host(mg.gemm(a, b, mode=mode, cfg=cfg, split_k=split))
+            assert np.array_equal(ref, got), (m, n, k, split, cfg)
+
+
 LARGE = [(mode, dist) for mode in MODES for dist in ("normal", "wide")]
 
 
