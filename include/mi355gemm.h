@@ -56,9 +56,14 @@ typedef enum {
  *   F32              float32  -- the paper's float product, on FP32 MFMA
  *   BF16, F16        bfloat16 / binary16 codes (uint16)
  *   F8E4M3           OCP FP8 E4M3 codes (uint8); C = scale_a*scale_b*(qA qB)
- *   F32_SPLIT_BF16X3 float32; each operand is split in-kernel into
+ *   F32_SPLIT_BF16X3 float32; each operand is split into
  *                    hi = RNE_bf16(x), lo = RNE_bf16(x - hi) and
- *                    C = hiA hiB + hiA loB + loA hiB (compensated BF16).   */
+ *                    C = hiA hiB + hiA loB + loA hiB (compensated BF16),
+ *                    the three products summed per 16 k in the order
+ *                    loA hiB, hiA loB, hiA hiB.  The split happens at
+ *                    tile staging, or (n a multiple of 8) once per operand
+ *                    into a library workspace of 6*k16*(m + n) bytes,
+ *                    k16 = k rounded up to 16; both give the same bits. */
 typedef enum {
     GEMM_MODE_F32 = 0,
     GEMM_MODE_BF16 = 1,
@@ -97,7 +102,9 @@ typedef struct gemm_problem {
 /* C = A*B for one problem, enqueued on `stream`.  The tile configuration
  * and split-K factor come from the tuning table (shape-keyed); split-K
  * partial sums go to a library-owned workspace and are summed in a fixed
- * order, so a given (mode, m, n, k) always produces the same bits. */
+ * order, so a given (mode, m, n, k) always produces the same bits.  The
+ * workspace (one per device and stream, grown on demand, kept until the
+ * process ends) also holds the split-BF16x3 operand copies. */
 int gemm_plain(const gemm_problem_t *p, void *stream);
 
 /* As gemm_plain with an explicit tile configuration (index into
