@@ -66,7 +66,8 @@ __device__ __forceinline__ f32x4 c32_load2(const float *__restrict__ P, int64_t 
     return v;
 }
 
-template <class Cfg>
+// CHECK = false: the whole blocks lie inside A and B (interior tiles).
+template <class Cfg, bool CHECK = true>
 __device__ __forceinline__ void c32_load_tiles(const TileProblem &P, int m0, int n0, int k0, f32x4 (&ra)[Cfg::AV],
                                                f32x4 (&rb)[Cfg::BV]) {
     const int tid = threadIdx.x;
@@ -77,14 +78,16 @@ __device__ __forceinline__ void c32_load_tiles(const TileProblem &P, int m0, int
         const int idx = tid + q * Cfg::THREADS;
         const int r = idx / (Cfg::BK / 2);
         const int kv = (idx % (Cfg::BK / 2)) * 2;
-        ra[q] = c32_load2(A, P.lda, m0 + r, k0 + kv, P.m, P.k);
+        if constexpr (CHECK) ra[q] = c32_load2(A, P.lda, m0 + r, k0 + kv, P.m, P.k);
+        else ra[q] = __builtin_bit_cast(f32x4, ld16(A + 2 * ((int64_t)(m0 + r) * P.lda + k0 + kv)));
     }
 #pragma unroll
     for (int q = 0; q < Cfg::BV; ++q) {
         const int idx = tid + q * Cfg::THREADS;
         const int kr = idx / (Cfg::BN / 2);
         const int cv = (idx % (Cfg::BN / 2)) * 2;
-        rb[q] = c32_load2(B, P.ldb, k0 + kr, n0 + cv, P.k, P.n);
+        if constexpr (CHECK) rb[q] = c32_load2(B, P.ldb, k0 + kr, n0 + cv, P.k, P.n);
+        else rb[q] = __builtin_bit_cast(f32x4, ld16(B + 2 * ((int64_t)(k0 + kr) * P.ldb + n0 + cv)));
     }
 }
 
@@ -217,13 +220,26 @@ __device__ __forceinline__ void c32_tile(const TileProblem &P, int tm, int tn, f
         c32_store_tiles<Cfg>(lds, ra, rbv);
     }
     __syncthreads();
-    for (int kt = 0; kt < nkt; ++kt) {
-        const int cur = kt & 1;
-        const bool more = kt + 1 < nkt;
-        if (more) c32_load_tiles<Cfg>(P, m0, n0, (kt + 1) * Cfg::BK, ra, rbv);
-        c32_compute_stage<Cfg>(lds + cur * Cfg::STAGE, re, im);
-        if (more) c32_store_tiles<Cfg>(lds + (cur ^ 1) * Cfg::STAGE, ra, rbv);
-        __syncthreads();
+    // interior tiles: unmasked loads (same arithmetic as the masked loop)
+    const bool interior = m0 + Cfg::BM <= P.m && n0 + Cfg::BN <= P.n && nkt * Cfg::BK <= P.k;
+    if (interior) {
+        for (int kt = 0; kt < nkt; ++kt) {
+            const int cur = kt & 1;
+            const bool more = kt + 1 < nkt;
+            if (more) c32_load_tiles<Cfg, false>(P, m0, n0, (kt + 1) * Cfg::BK, ra, rbv);
+            c32_compute_stage<Cfg>(lds + cur * Cfg::STAGE, re, im);
+            if (more) c32_store_tiles<Cfg>(lds + (cur ^ 1) * Cfg::STAGE, ra, rbv);
+            __syncthreads();
+        }
+    } else {
+        for (int kt = 0; kt < nkt; ++kt) {
+            const int cur = kt & 1;
+            const bool more = kt + 1 < nkt;
+            if (more) c32_load_tiles<Cfg>(P, m0, n0, (kt + 1) * Cfg::BK, ra, rbv);
+            c32_compute_stage<Cfg>(lds + cur * Cfg::STAGE, re, im);
+            if (more) c32_store_tiles<Cfg>(lds + (cur ^ 1) * Cfg::STAGE, ra, rbv);
+            __syncthreads();
+        }
     }
     c32_epilogue<Cfg>(P.C, P.ldc, P.m, P.n, m0, n0, re, im);
 }

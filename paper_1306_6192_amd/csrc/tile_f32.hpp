@@ -78,7 +78,9 @@ __device__ __forceinline__ f32x4 f32_load4(const float *__restrict__ P, int64_t 
     return v;
 }
 
-template <class Cfg>
+// CHECK = false: the caller guarantees that the whole BM x BK and BK x BN
+// blocks lie inside A and B (interior tiles), so the loads need no masks.
+template <class Cfg, bool CHECK = true>
 __device__ __forceinline__ void f32_load_tiles(const TileProblem &P, int m0, int n0, int k0,
                                                f32x4 (&ra)[Cfg::AV], f32x4 (&rb)[Cfg::BV]) {
     const int tid = threadIdx.x;
@@ -89,14 +91,20 @@ __device__ __forceinline__ void f32_load_tiles(const TileProblem &P, int m0, int
         const int idx = tid + q * Cfg::THREADS;
         const int r = idx / (Cfg::BK / 4);
         const int kv = (idx % (Cfg::BK / 4)) * 4;
-        ra[q] = f32_load4(A, P.lda, m0 + r, k0 + kv, P.m, P.k);
+        if constexpr (CHECK)
+            ra[q] = f32_load4(A, P.lda, m0 + r, k0 + kv, P.m, P.k);
+        else
+            ra[q] = __builtin_bit_cast(f32x4, ld16(A + (int64_t)(m0 + r) * P.lda + k0 + kv));
     }
 #pragma unroll
     for (int q = 0; q < Cfg::BV; ++q) {
         const int idx = tid + q * Cfg::THREADS;
         const int kr = idx / (Cfg::BN / 4);
         const int cv = (idx % (Cfg::BN / 4)) * 4;
-        rb[q] = f32_load4(B, P.ldb, k0 + kr, n0 + cv, P.k, P.n);
+        if constexpr (CHECK)
+            rb[q] = f32_load4(B, P.ldb, k0 + kr, n0 + cv, P.k, P.n);
+        else
+            rb[q] = __builtin_bit_cast(f32x4, ld16(B + (int64_t)(k0 + kr) * P.ldb + n0 + cv));
     }
 }
 
@@ -179,13 +187,28 @@ __device__ __forceinline__ void f32_tile(const TileProblem &P, int tm, int tn, i
         f32_store_tiles<Cfg>(lds, ra, rbv);
     }
     __syncthreads();
-    for (int kt = kt0; kt < kt1; ++kt) {
-        const int cur = (kt - kt0) & 1;
-        const bool more = kt + 1 < kt1;
-        if (more) f32_load_tiles<Cfg>(P, m0, n0, (kt + 1) * Cfg::BK, ra, rbv);
-        f32_compute_stage<Cfg>(lds + cur * Cfg::STAGE, acc);
-        if (more) f32_store_tiles<Cfg>(lds + (cur ^ 1) * Cfg::STAGE, ra, rbv);
-        __syncthreads();
+    // Interior tiles (the whole tile and every k-tile inside the matrices)
+    // run a loop whose loads carry no masks; edge tiles the masked one.  Both
+    // do the same arithmetic in the same order.
+    const bool interior = m0 + Cfg::BM <= P.m && n0 + Cfg::BN <= P.n && kt1 * Cfg::BK <= P.k;
+    if (interior) {
+        for (int kt = kt0; kt < kt1; ++kt) {
+            const int cur = (kt - kt0) & 1;
+            const bool more = kt + 1 < kt1;
+            if (more) f32_load_tiles<Cfg, false>(P, m0, n0, (kt + 1) * Cfg::BK, ra, rbv);
+            f32_compute_stage<Cfg>(lds + cur * Cfg::STAGE, acc);
+            if (more) f32_store_tiles<Cfg>(lds + (cur ^ 1) * Cfg::STAGE, ra, rbv);
+            __syncthreads();
+        }
+    } else {
+        for (int kt = kt0; kt < kt1; ++kt) {
+            const int cur = (kt - kt0) & 1;
+            const bool more = kt + 1 < kt1;
+            if (more) f32_load_tiles<Cfg>(P, m0, n0, (kt + 1) * Cfg::BK, ra, rbv);
+            f32_compute_stage<Cfg>(lds + cur * Cfg::STAGE, acc);
+            if (more) f32_store_tiles<Cfg>(lds + (cur ^ 1) * Cfg::STAGE, ra, rbv);
+            __syncthreads();
+        }
     }
 
     float *C;
