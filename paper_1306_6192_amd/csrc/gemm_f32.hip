@@ -1,7 +1,10 @@
-// FP32 product kernels: the plain launch for every tile configuration and
-// the grouped persistent launch (128x128 and 64x64 tiles).
+// FP32 product kernels: the plain launch for every tile configuration
+// (register-staged tiles for any shape; asynchronous-copy tiles for shapes
+// whose k, n and row strides are whole 16-byte chunks) and the grouped
+// persistent launch (128x128 and 64x64 tiles).
 #include "kernels_impl.hpp"
 #include "tile_f32.hpp"
+#include "tile_lp2.hpp"
 
 static const KernelCfg kF32Configs[] = {
     make_cfg<F32Cfg<256, 256>, 1>(),
@@ -17,6 +20,18 @@ static const KernelCfg kF32Configs[] = {
     make_cfg<F32Cfg<256, 256, 4, 2>, 2>(),
     make_cfg<F32Cfg<256, 128, 4, 2>, 2>(),   // eight waves, 64 x 64 each
     make_cfg<F32Cfg<128, 256, 2, 4>, 2>(),
+    // asynchronous-copy tiles (four-stage LDS ring, k-tiles of 16): eight
+    // waves (two per SIMD) at 2 x 4 and 4 x 2, four waves with 128 x 128
+    // per wave (one per SIMD, accumulators in AGPRs), eight waves on
+    // 128 x 256, four waves on 128 x 128 (two workgroups per CU), four waves
+    // on 256 x 128 and 128 x 256
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 256, 4, 2, 4>, 2, 4>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 256, 4, 4, 2>, 2, 4>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 256, 4>, 1, 4>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 128, 256, 4, 2, 4>, 2, 4>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 128, 128, 4>, 2, 4>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 128, 4>, 1, 4>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 128, 256, 4>, 1, 4>(),
 };
 
 const KernelCfg *f32_configs(int *count) {

@@ -1,15 +1,22 @@
-// Reduced-precision output tile, asynchronous-copy variant (BF16, F16, FP8).
+// Asynchronous-copy output tile (BF16, F16, FP8, and FP32).
 //
-// Same arithmetic as tile_lp.hpp (same MFMA instructions, same k order, so
-// the two produce identical bits), different data movement:
+// Same arithmetic as the register-staged tiles (tile_lp.hpp for BF16, F16
+// and FP8, tile_f32.hpp for FP32: same MFMA instructions, same k order, so
+// each pair produces identical bits), different data movement:
 //   * A and B go from HBM straight into LDS with 16-byte direct loads
 //     (global_load_lds_dwordx4): no staging registers and no register
 //     transpose; lane L of one such load lands at LDS base + 16*L.
 //   * A ring of STAGES LDS buffers keeps STAGES-1 k-tiles in flight while one
 //     is consumed; each wave waits (vmcnt) only for its own oldest tile and one
 //     barrier per k-tile publishes it.
-//   * B stays row-major (k x n) in LDS; the MFMA B operand (consecutive k of
-//     one column per lane) is gathered with the transposing LDS reads
+//   * FP32 (v_mfma_f32_32x32x2_f32): one k-step is 8 consecutive k, read as
+//     one 16-byte A chunk per lane (k = 8c + 4(l/32) .. + 3, as in
+//     tile_f32.hpp) and, per MFMA t = 0..3, the CB consecutive floats of B row
+//     8c + 4(l/32) + t at column CB*(l%32) of the wave's columns; B rows need
+//     no swizzle (32 lanes read 32 consecutive 8- or 16-byte pieces).
+//   * 16- and 8-bit B stays row-major (k x n) in LDS; the MFMA B operand
+//     (consecutive k of one column per lane) is gathered with the transposing
+//     LDS reads
 //     ds_read_b64_tr_b16 / ds_read_b64_tr_b8.  Within each group of 16 lanes,
 //     lane j receives element j%4 (b16; j%8 for b8) of the 8-byte chunk
 //     addressed by lane 4r + j/4 (b8: 2r + j/8), for r = 0..3 (b8: 0..7); so
@@ -19,8 +26,9 @@
 //     of 16 (A) or 4-8 (B) consecutive rows hit distinct LDS banks; the
 //     swizzle is applied on the global side of the direct loads (each lane
 //     picks which logical chunk it fetches), since the LDS side is fixed.
-// Shape requirements (checked on the host; other shapes use tile_lp.hpp):
-// k and n multiples of the 16-byte chunk (8 x 16-bit or 16 x 8-bit), row
+// Shape requirements (checked on the host; other shapes use the
+// register-staged tiles): k and n multiples of the 16-byte chunk (4 x 32-bit,
+// 8 x 16-bit or 16 x 8-bit), row
 // strides multiples of 16 bytes, 16-byte aligned A and B.  Rows of A beyond m
 // and columns of B beyond n read clamped (valid, finite) data whose results
 // are never stored; k beyond the end reads a zero chunk.
@@ -54,12 +62,17 @@ struct Lp2Cfg {
     static constexpr int THREADS = 64 * WAVES;
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int RB = TM / 32, CB = TN / 32;
-    static constexpr int ESZ = (MODE == GEMM_MODE_F8E4M3) ? 1 : 2;
+    static constexpr bool F32 = (MODE == GEMM_MODE_F32);
+    static constexpr int ESZ = (MODE == GEMM_MODE_F8E4M3) ? 1 : F32 ? 4 : 2;
     static constexpr int CE = 16 / ESZ;                 // elements per 16-byte chunk
     static constexpr int BK = 64 / ESZ;                 // k per k-tile: 64-byte A rows
-    static constexpr int KCH = (MODE == GEMM_MODE_F8E4M3) ? 64 : 16;   // k per MFMA
-    static constexpr int MFMA_K = KCH;
+    // k per step: one MFMA (16- and 8-bit), four 32x32x2 MFMAs (FP32)
+    static constexpr int KCH = (MODE == GEMM_MODE_F8E4M3) ? 64 : F32 ? 8 : 16;
+    static constexpr int MFMA_K = F32 ? 2 : KCH;
     static constexpr int STEPS = BK / KCH;
+    static constexpr int NPB = F32 ? 4 : CB;            // B fragment reads per step
+    static constexpr int NP = RB + NPB;                 // fragment reads per step
+    static constexpr int NM = RB * CB * (F32 ? 4 : 1);  // MFMAs per step
     static constexpr int A_ROWB = 64;
     static constexpr int B_ROWB = BN * ESZ;
     static constexpr int B_CPR = B_ROWB / 16;           // 16-byte chunks per B row
@@ -83,6 +96,7 @@ struct Lp2Cfg {
     // gives those 16 rows distinct banks (and 8 consecutive rows too).
     __device__ static __forceinline__ int a_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
     __device__ static __forceinline__ int b_swz(int k) {
+        if constexpr (F32) return 0;
         return (ESZ == 2 ? 4 * (k & 3) : 2 * (k & 7)) & (B_CPR - 1);
     }
     __device__ static void run(const TileProblem &P, int tm, int tn, int split, uint8_t *lds);
@@ -176,22 +190,34 @@ __device__ __forceinline__ void lp2_issue(const Lp2Src<Cfg> &S, int k0, uint32_t
 }
 
 // MFMA operand fragments of one k-step (KCH consecutive k) for the wave's
-// RB x CB accumulator blocks.
-template <class Cfg, bool FP8 = (Cfg::MODE == GEMM_MODE_F8E4M3)>
+// RB x CB accumulator blocks.  Kind 0: 16-bit, 1: FP8, 2: FP32 (b[t] holds
+// the CB values of MFMA t, one per accumulator block column).
+template <int CB> struct Lp2FVec;
+template <> struct Lp2FVec<1> { typedef float T; };
+template <> struct Lp2FVec<2> { typedef f32x2 T; };
+template <> struct Lp2FVec<4> { typedef f32x4 T; };
+
+template <class Cfg, int KIND = (Cfg::MODE == GEMM_MODE_F8E4M3) ? 1 : Cfg::F32 ? 2 : 0>
 struct Lp2Frag;
 template <class Cfg>
-struct Lp2Frag<Cfg, false> {
+struct Lp2Frag<Cfg, 0> {
     u32x4 a[Cfg::RB];
     u32x4 b[Cfg::CB];
 };
 template <class Cfg>
-struct Lp2Frag<Cfg, true> {
+struct Lp2Frag<Cfg, 1> {
     i32x8 a[Cfg::RB];
     i32x8 b[Cfg::CB];
 };
+template <class Cfg>
+struct Lp2Frag<Cfg, 2> {
+    f32x4 a[Cfg::RB];
+    typename Lp2FVec<Cfg::CB>::T b[4];
+};
 
 // Read piece p of the fragments of k-step kc of the k-tile held in `stage`:
-// p < RB is A row block p, otherwise B column block p - RB.
+// p < RB is A row block p, otherwise B column block p - RB (FP32: the B
+// values of MFMA p - RB for all CB column blocks).
 template <class Cfg>
 __device__ __forceinline__ void lp2_read_piece(const uint8_t *stage, int kc, int p, Lp2Frag<Cfg> &F) {
     const int lane = threadIdx.x & 63;
@@ -201,7 +227,17 @@ __device__ __forceinline__ void lp2_read_piece(const uint8_t *stage, int kc, int
     const int p16 = lane & 15, G = lane >> 4;
     const uint8_t *As = stage;
     const uint8_t *Bs = stage + Cfg::A_STAGE;
-    if constexpr (Cfg::MODE == GEMM_MODE_F8E4M3) {
+    if constexpr (Cfg::F32) {
+        if (p < Cfg::RB) {
+            const int r = wm * Cfg::TM + p * 32 + l32;
+            F.a[p] = *reinterpret_cast<const f32x4 *>(As + r * Cfg::A_ROWB + 16 * ((2 * kc + g) ^ Cfg::a_swz(r)));
+        } else {
+            const int t = p - Cfg::RB;
+            const int k = 8 * kc + 4 * g + t;
+            const float *row = reinterpret_cast<const float *>(Bs + k * Cfg::B_ROWB);
+            F.b[t] = *reinterpret_cast<const typename Lp2FVec<Cfg::CB>::T *>(row + wn * Cfg::TN + Cfg::CB * l32);
+        }
+    } else if constexpr (Cfg::MODE == GEMM_MODE_F8E4M3) {
         if (p < Cfg::RB) {
             const int rb = p;
             const int r = wm * Cfg::TM + rb * 32 + l32;
@@ -247,21 +283,33 @@ __device__ __forceinline__ void lp2_read_piece(const uint8_t *stage, int kc, int
 template <class Cfg>
 __device__ __forceinline__ void lp2_read(const uint8_t *stage, int kc, Lp2Frag<Cfg> &F) {
 #pragma unroll
-    for (int p = 0; p < Cfg::RB + Cfg::CB; ++p) lp2_read_piece<Cfg>(stage, kc, p, F);
+    for (int p = 0; p < Cfg::NP; ++p) lp2_read_piece<Cfg>(stage, kc, p, F);
 }
 
-// The MFMA of accumulator block (rb, cb) for one k-step.
+// MFMA i (0 .. NM-1) of one k-step.  16- and 8-bit: the one MFMA of
+// accumulator block (i / CB, i % CB).  FP32: MFMA t = i / (RB CB) of block
+// ((i / CB) % RB, i % CB), so that consecutive MFMAs feed different
+// accumulators and each block sums t = 0, 1, 2, 3 in order.
 template <class Cfg>
-__device__ __forceinline__ void lp2_mfma1(const Lp2Frag<Cfg> &F, f32x16 (&acc)[Cfg::RB][Cfg::CB], int rb, int cb) {
-    if constexpr (Cfg::MODE == GEMM_MODE_F8E4M3)
-        acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(F.a[rb], F.b[cb], acc[rb][cb], 0, 0, 0, 0,
-                                                                     0, 0);
-    else if constexpr (Cfg::MODE == GEMM_MODE_BF16)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            __builtin_bit_cast(bf16x8, F.a[rb]), __builtin_bit_cast(bf16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
-    else
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-            __builtin_bit_cast(f16x8, F.a[rb]), __builtin_bit_cast(f16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
+__device__ __forceinline__ void lp2_mfma1(const Lp2Frag<Cfg> &F, f32x16 (&acc)[Cfg::RB][Cfg::CB], int i) {
+    if constexpr (Cfg::F32) {
+        const int t = i / (Cfg::RB * Cfg::CB), rb = (i / Cfg::CB) % Cfg::RB, cb = i % Cfg::CB;
+        float bv;
+        if constexpr (Cfg::CB == 1) bv = F.b[t];
+        else bv = F.b[t][cb];
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(F.a[rb][t], bv, acc[rb][cb], 0, 0, 0);
+    } else {
+        const int rb = i / Cfg::CB, cb = i % Cfg::CB;
+        if constexpr (Cfg::MODE == GEMM_MODE_F8E4M3)
+            acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(F.a[rb], F.b[cb], acc[rb][cb], 0, 0, 0,
+                                                                         0, 0, 0);
+        else if constexpr (Cfg::MODE == GEMM_MODE_BF16)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, F.a[rb]), __builtin_bit_cast(bf16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
+        else
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                __builtin_bit_cast(f16x8, F.a[rb]), __builtin_bit_cast(f16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
+    }
 }
 
 // Natural-column epilogue: lane l%32 of accumulator block cb holds output
@@ -311,14 +359,15 @@ template <class Cfg, bool BOUNDARY, bool CHECK>
 __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, int u, int kc, uint8_t *lds,
                                          const Lp2Frag<Cfg> &cur, Lp2Frag<Cfg> &nxt,
                                          f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
-    constexpr int NP = Cfg::RB + Cfg::CB;           // fragment pieces per step
-    constexpr int NM = Cfg::RB * Cfg::CB;           // MFMAs per step
+    constexpr int NP = Cfg::NP;                     // fragment pieces per step
+    constexpr int NM = Cfg::NM;                     // MFMAs per step
     if constexpr (BOUNDARY) {
-        constexpr int H = ((Cfg::RB + 1) / 2) * Cfg::CB;   // MFMAs before the barrier
+        // MFMAs before the barrier
+        constexpr int H = Cfg::F32 ? NM / 2 : ((Cfg::RB + 1) / 2) * Cfg::CB;
         constexpr int W = NP + Cfg::LOADS;                 // work items after it
         constexpr int PER = (W + (NM - H) - 1) / (NM - H);
 #pragma unroll
-        for (int t = 0; t < H; ++t) lp2_mfma1<Cfg>(cur, acc, t / Cfg::CB, t % Cfg::CB);
+        for (int t = 0; t < H; ++t) lp2_mfma1<Cfg>(cur, acc, t);
         __builtin_amdgcn_sched_barrier(0);
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         wait_vmcnt<(Cfg::STAGES - 2) * Cfg::LOADS>();
@@ -327,7 +376,7 @@ __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, i
         const int k0 = (kt0 + i + Cfg::STAGES) * Cfg::BK;
 #pragma unroll
         for (int t = H; t < NM; ++t) {
-            lp2_mfma1<Cfg>(cur, acc, t / Cfg::CB, t % Cfg::CB);
+            lp2_mfma1<Cfg>(cur, acc, t);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int w = (t - H) * PER; w < (t - H + 1) * PER && w < W; ++w) {
@@ -338,11 +387,13 @@ __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, i
         }
     } else {
         const uint8_t *here = lds + u * Cfg::STAGE;
+        // FP32 steps have four times the MFMAs: one read after every other one
+        constexpr int SPREAD = Cfg::F32 ? 2 : 1;
 #pragma unroll
         for (int t = 0; t < NM; ++t) {
-            lp2_mfma1<Cfg>(cur, acc, t / Cfg::CB, t % Cfg::CB);
+            lp2_mfma1<Cfg>(cur, acc, t);
             __builtin_amdgcn_sched_barrier(0);
-            if (t < NP) lp2_read_piece<Cfg>(here, kc + 1, t, nxt);
+            if (t % SPREAD == 0 && t / SPREAD < NP) lp2_read_piece<Cfg>(here, kc + 1, t / SPREAD, nxt);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -368,14 +419,19 @@ template <class Cfg, bool CHECK>
 __device__ __forceinline__ void lp2_pair(const Lp2Src<Cfg> &S, int kt0, int i, int u, int nt, bool guard,
                                          uint8_t *lds, Lp2Frag<Cfg> &f0, Lp2Frag<Cfg> &f1,
                                          f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
-    if (!guard || i < nt) {
-        if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg, CHECK>(S, kt0, i, u, lds, f0, f1, acc);
-        else lp2_ktile<Cfg, CHECK>(S, kt0, i, u, lds, f0, f1, acc);
-    }
+    if (!guard || i < nt) lp2_ktile<Cfg, CHECK>(S, kt0, i, u, lds, f0, f1, acc);
     if (!guard || i + 1 < nt) {
         if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg, CHECK>(S, kt0, i + 1, u + 1, lds, f0, f1, acc);
         else lp2_ktile<Cfg, CHECK>(S, kt0, i + 1, u + 1, lds, f1, f0, acc);
     }
+}
+
+// One round: the STAGES k-tiles i .. i + STAGES - 1, one per stage, in pairs.
+template <class Cfg, bool CHECK>
+__device__ __forceinline__ void lp2_round(const Lp2Src<Cfg> &S, int kt0, int i, int nt, bool guard, uint8_t *lds,
+                                          Lp2Frag<Cfg> &f0, Lp2Frag<Cfg> &f1, f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+#pragma unroll
+    for (int u = 0; u < Cfg::STAGES; u += 2) lp2_pair<Cfg, CHECK>(S, kt0, i + u, u, nt, guard, lds, f0, f1, acc);
 }
 
 template <class Cfg>
@@ -413,19 +469,10 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
         int i = 0;
         // rounds whose refills (k-tiles i + STAGES .. i + 2 STAGES - 1) are
         // whole: no k bound on the loads
-        for (; i + 2 * Cfg::STAGES <= nfull; i += Cfg::STAGES) {
-#pragma unroll
-            for (int u = 0; u < Cfg::STAGES; u += 2)
-                lp2_pair<Cfg, false>(S, kt0, i + u, u, nt, false, lds, f0, f1, acc);
-        }
-        for (; i + Cfg::STAGES <= nt; i += Cfg::STAGES) {
-#pragma unroll
-            for (int u = 0; u < Cfg::STAGES; u += 2)
-                lp2_pair<Cfg, true>(S, kt0, i + u, u, nt, false, lds, f0, f1, acc);
-        }
+        for (; i + 2 * Cfg::STAGES <= nfull; i += Cfg::STAGES) lp2_round<Cfg, false>(S, kt0, i, nt, false, lds, f0, f1, acc);
+        for (; i + Cfg::STAGES <= nt; i += Cfg::STAGES) lp2_round<Cfg, true>(S, kt0, i, nt, false, lds, f0, f1, acc);
         // the last nt mod STAGES k-tiles (stages 0 ..)
-#pragma unroll
-        for (int u = 0; u < Cfg::STAGES; u += 2) lp2_pair<Cfg, true>(S, kt0, i + u, u, nt, true, lds, f0, f1, acc);
+        lp2_round<Cfg, true>(S, kt0, i, nt, true, lds, f0, f1, acc);
         wait_vmcnt<0>();   // the loads past the end have landed before the ring is reused
     }
     __syncthreads();       // the LDS ring may be refilled by this workgroup's next tile
@@ -433,7 +480,8 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
     int64_t ldc;
     float scale;
     epilogue_target(P, split, C, ldc, scale);
-    lp2_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
+    if constexpr (Cfg::F32) tile_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
+    else lp2_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
 }
 
 template <int MODE, int BM, int BN, int STAGES, int WM, int WN>

@@ -105,9 +105,13 @@ def test_config_tables():
     for c in range(n):
         assert lib.gemm_config_info(0, c, info) == 0
         bm, bn, bk, waves, lds, mk = list(info)
-        assert bm % 32 == 0 and bn % 32 == 0 and bk == 32 and waves in (4, 8) and 0 < lds <= 160 * 1024
-        seen.add((bm, bn, waves))
-    assert len(seen) >= n - 1   # the two 8-wave 256x256 tiles differ only in their wave grid
+        # register-staged tiles take k-tiles of 32, asynchronous-copy ones 16
+        assert bm % 32 == 0 and bn % 32 == 0 and bk in (16, 32) and waves in (4, 8) and 0 < lds <= 160 * 1024
+        assert mk == 2
+        seen.add((bm, bn, bk, waves))
+    # tiles of one size and wave count differ in their wave grid or pipeline
+    # (one barrier per k-tile or per two), so only the distinct sizes count
+    assert len(seen) >= 8
     assert lib.gemm_config_info(0, n, info) == _lib.GEMM_EINVAL
     assert lib.gemm_num_configs(9) == _lib.GEMM_EINVAL
 

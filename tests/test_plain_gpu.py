@@ -135,6 +135,62 @@ def test_repeat_and_cross_config_bitwise():
     assert np.array_equal(s3, host(mg.gemm(dA, dB, cfg=3, split_k=3)))
 
 
+# k and n whole 16-byte chunks (multiples of 4 floats): the asynchronous-copy
+# tiles run these; ragged m, n not a multiple of the tile, k with a partial
+# k-tile of 16, one-row and one-chunk extremes
+CHUNKED_SHAPES = [(1, 4, 4), (33, 36, 20), (64, 512, 16), (129, 388, 8), (257, 132, 1036), (300, 208, 1040),
+                  (513, 260, 4100)]
+
+
+def _chunked_configs():
+    return [c for c in _configs() if mg.config_info(mg.MODE_F32, c)["BK"] == 16]
+
+
+@pytest.mark.parametrize("m,n,k", CHUNKED_SHAPES)
+def test_async_tiles_chunked_shapes(m, n, k):
+    """The asynchronous-copy FP32 tiles on shapes they accept: within the
+    float32 bound of the oracle, and bit for bit equal to the register-staged
+    tile (same MFMA sequence per element), with and without split-K."""
+    log(f"plain f32 async tiles {(m, n, k)}")
+    A, B = synth.pair(m, n, k, seed=m + 5 * n + 11 * k, dist="normal")
+    R = oracle.gemm(A, B)
+    absAB = abs_product(A, B)
+    dA, dB = dev(A), dev(B)
+    assert _chunked_configs()
+    for split in (1, 3):
+        ref = host(mg.gemm(dA, dB, cfg=0, split_k=split))
+        for cfg in _chunked_configs():
+            C = host(mg.gemm(dA, dB, cfg=cfg, split_k=split))
+            assert_within_bound(C, R, absAB, k, f"shape {(m, n, k)} cfg {cfg} split {split}")
+            assert np.array_equal(C, ref), (cfg, split)
+
+
+def test_async_tiles_strides_and_fallback():
+    """Padded row strides that stay whole chunks run the asynchronous-copy
+    tiles; a base pointer off 16-byte alignment or a stride that is not a
+    whole chunk falls back to the register-staged tile of the same size.  All
+    give the same bits and leave the frame around C untouched."""
+    log("plain f32 async tiles strides/fallback")
+    m, n, k = 200, 132, 520
+    A, B = synth.pair(m, n, k, seed=31, dist="normal")
+    ref = host(mg.gemm(dev(A), dev(B), cfg=0, split_k=1))
+    for pad_a, pad_b, off in [(4, 8, 0), (3, 4, 0), (4, 8, 1)]:
+        bigA = torch.zeros((m, k + pad_a + off), device="cuda")
+        bigB = torch.zeros((k, n + pad_b + off), device="cuda")
+        dA = bigA[:, off:off + k]
+        dB = bigB[:, off:off + n]
+        dA.copy_(dev(A))
+        dB.copy_(dev(B))
+        for cfg in _chunked_configs():
+            big = torch.full((m + 2, n + 2), -7.0, device="cuda")
+            mg.gemm(dA, dB, out=big[1:m + 1, 1:n + 1], cfg=cfg, split_k=1)
+            h = host(big)
+            assert np.array_equal(h[1:m + 1, 1:n + 1], ref), (pad_a, pad_b, off, cfg)
+            frame = np.ones(h.shape, bool)
+            frame[1:m + 1, 1:n + 1] = False
+            assert np.all(h[frame] == -7.0)
+
+
 def test_empty_and_k_zero():
     log("plain f32 empty/k=0")
     out = torch.full((5, 7), 3.0, device="cuda")
