@@ -219,6 +219,9 @@ def section_plain(args, torch, mg, synth, stream, line):
         R = ref_sampled(A, B, rows, cols)
         per_shape.append({"m": m, "n": n, "k": k, "ms_avg": round(avg, 4), "ms_min": round(float(np.min(ms)), 4),
                           "tflops": round(tf, 2), "frac_peak": round(tf / PEAK["f32"], 4),
+                          # operands read once and C written once, per unit time
+                          "alg_bytes": 4 * (m * k + k * n + m * n),
+                          "alg_hbm_gb_per_s": round(4.0 * (m * k + k * n + m * n) / (avg / 1e3) / 1e9, 1),
                           "cfg": mg.config_info(mg.MODE_F32, cfg), "split_k": split,
                           "rel_err_sampled": relerr(C[rows, cols], R)})
         if (m, n, k) == DOMINANT:
