@@ -51,6 +51,21 @@ static int enqueue_ext(int mode, int64_t m, int64_t n, int64_t k, const void *A,
     const KernelCfg *t = configs(mode, &count);
     if (!t || count == 0) return fail(GEMM_EUNSUPPORTED, "mode %d has no kernels", mode);
     if (cfg < 0 || cfg >= count) return fail(GEMM_EINVAL, "config %d out of range [0,%d)", cfg, count);
+    {
+        // an asynchronous-copy configuration needs whole 16-byte chunks;
+        // otherwise its register-staged counterpart of the same tile runs
+        gemm_problem_t p;
+        memset(&p, 0, sizeof(p));
+        p.mode = mode;
+        p.m = m;
+        p.n = n;
+        p.k = k;
+        p.A = A;
+        p.lda = lda;
+        p.B = B;
+        p.ldb = ldb;
+        cfg = effective_cfg(p, cfg);
+    }
     const KernelCfg &kc = t[cfg];
     TileProblem P;
     memset(&P, 0, sizeof(P));

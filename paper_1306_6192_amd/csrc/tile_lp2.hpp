@@ -1,8 +1,9 @@
-// Asynchronous-copy output tile (BF16, F16, FP8, and FP32).
+// Asynchronous-copy output tile (BF16, F16, FP8, FP32 and binary64).
 //
 // Same arithmetic as the register-staged tiles (tile_lp.hpp for BF16, F16
-// and FP8, tile_f32.hpp for FP32: same MFMA instructions, same k order, so
-// each pair produces identical bits), different data movement:
+// and FP8, tile_f32.hpp for FP32, tile_f64.hpp for binary64: same MFMA
+// instructions, same k order, so each pair produces identical bits),
+// different data movement:
 //   * A and B go from HBM straight into LDS with 16-byte direct loads
 //     (global_load_lds_dwordx4): no staging registers and no register
 //     transpose; lane L of one such load lands at LDS base + 16*L.
@@ -14,6 +15,11 @@
 //     tile_f32.hpp) and, per MFMA t = 0..3, the CB consecutive floats of B row
 //     8c + 4(l/32) + t at column CB*(l%32) of the wave's columns; B rows need
 //     no swizzle (32 lanes read 32 consecutive 8- or 16-byte pieces).
+//   * binary64 (v_mfma_f64_16x16x4_f64, 16x16 accumulator blocks): A rows of
+//     a k-tile are 128 bytes (16 doubles, the register-staged tile's k-tile),
+//     one step per k-tile: lane (l%16, g = l/16) reads doubles 4g .. 4g + 3
+//     of its row as two 16-byte chunks, and MFMA t = 0..3 takes k = 4g + t;
+//     B row 4g + t is read at the column pairs 32h + 2(l%16) of tile_f64.hpp.
 //   * 16- and 8-bit B stays row-major (k x n) in LDS; the MFMA B operand
 //     (consecutive k of one column per lane) is gathered with the transposing
 //     LDS reads
@@ -27,14 +33,17 @@
 //     swizzle is applied on the global side of the direct loads (each lane
 //     picks which logical chunk it fetches), since the LDS side is fixed.
 // Shape requirements (checked on the host; other shapes use the
-// register-staged tiles): k and n multiples of the 16-byte chunk (4 x 32-bit,
-// 8 x 16-bit or 16 x 8-bit), row
+// register-staged tiles): k and n multiples of the 16-byte chunk (2 x 64-bit,
+// 4 x 32-bit, 8 x 16-bit or 16 x 8-bit), row
 // strides multiples of 16 bytes, 16-byte aligned A and B.  Rows of A beyond m
 // and columns of B beyond n read clamped (valid, finite) data whose results
 // are never stored; k beyond the end reads a zero chunk.
 #pragma once
 
+#include <type_traits>
+
 #include "tile_common.hpp"
+#include "tile_f64.hpp"
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
@@ -60,20 +69,26 @@ struct Lp2Cfg {
     static constexpr int WM = WM_, WN = WN_;            // waves along m and n
     static constexpr int WAVES = WM * WN;
     static constexpr int THREADS = 64 * WAVES;
-    static constexpr int TM = BM / WM, TN = BN / WN;
-    static constexpr int RB = TM / 32, CB = TN / 32;
     static constexpr bool F32 = (MODE == GEMM_MODE_F32);
-    static constexpr int ESZ = (MODE == GEMM_MODE_F8E4M3) ? 1 : F32 ? 4 : 2;
+    static constexpr bool F64 = (MODE == GEMM_MODE_F64);
+    static constexpr int BLK = F64 ? 16 : 32;           // accumulator block edge
+    static constexpr int TM = BM / WM, TN = BN / WN;
+    static constexpr int RB = TM / BLK, CB = TN / BLK;
+    static constexpr int ESZ = (MODE == GEMM_MODE_F8E4M3) ? 1 : F64 ? 8 : F32 ? 4 : 2;
     static constexpr int CE = 16 / ESZ;                 // elements per 16-byte chunk
-    static constexpr int BK = 64 / ESZ;                 // k per k-tile: 64-byte A rows
-    // k per step: one MFMA (16- and 8-bit), four 32x32x2 MFMAs (FP32)
-    static constexpr int KCH = (MODE == GEMM_MODE_F8E4M3) ? 64 : F32 ? 8 : 16;
-    static constexpr int MFMA_K = F32 ? 2 : KCH;
+    static constexpr int A_ROWB = F64 ? 128 : 64;       // bytes of an A row per k-tile
+    static constexpr int A_CPR = A_ROWB / 16;           // 16-byte chunks per A row
+    static constexpr int BK = A_ROWB / ESZ;             // k per k-tile
+    // k per step: one MFMA (16- and 8-bit), four 32x32x2 MFMAs (FP32), four
+    // 16x16x4 MFMAs (binary64)
+    static constexpr int KCH = (MODE == GEMM_MODE_F8E4M3) ? 64 : F64 ? 16 : F32 ? 8 : 16;
+    static constexpr int MFMA_K = F32 ? 2 : F64 ? 4 : KCH;
     static constexpr int STEPS = BK / KCH;
-    static constexpr int NPB = F32 ? 4 : CB;            // B fragment reads per step
+    static constexpr bool FOUR = F32 || F64;            // four MFMAs per block per step
+    static constexpr int NPB = FOUR ? 4 : CB;           // B fragment reads per step
     static constexpr int NP = RB + NPB;                 // fragment reads per step
-    static constexpr int NM = RB * CB * (F32 ? 4 : 1);  // MFMAs per step
-    static constexpr int A_ROWB = 64;
+    static constexpr int NM = RB * CB * (FOUR ? 4 : 1); // MFMAs per step
+    typedef typename std::conditional<F64, f64x4, f32x16>::type Acc;
     static constexpr int B_ROWB = BN * ESZ;
     static constexpr int B_CPR = B_ROWB / 16;           // 16-byte chunks per B row
     static constexpr int A_STAGE = BM * A_ROWB;
@@ -90,13 +105,18 @@ struct Lp2Cfg {
     static_assert(STAGES >= 2 && (STAGES - 1) * LOADS < 64, "vmcnt range");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
     // physical chunk of logical chunk c in A row r / B row k
-    // A rows are 64 bytes (4 chunks); a fragment read of 16 consecutive rows
-    // (one 16-lane phase of a 16-byte LDS read on the 64 banks) touches 4
-    // rows of each (r mod 4) class: XOR-ing the chunk with bits 1-2 of the row
-    // gives those 16 rows distinct banks (and 8 consecutive rows too).
-    __device__ static __forceinline__ int a_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+    // 64-byte A rows (4 chunks): a fragment read of 16 consecutive rows (one
+    // 16-lane phase of a 16-byte LDS read on the 64 banks) touches 4 rows of
+    // each (r mod 4) class: XOR-ing the chunk with bits 1-2 of the row gives
+    // those 16 rows distinct banks (and 8 consecutive rows too).  128-byte
+    // rows (8 chunks): 16 rows hold 2 of each (r mod 2) class, and bits 1-3
+    // of the row spread each class over 8 chunks.
+    __device__ static __forceinline__ int a_swz(int r) {
+        if constexpr (A_CPR == 8) return (r >> 1) & 7;
+        return ((r >> 1) ^ (r >> 2)) & 3;
+    }
     __device__ static __forceinline__ int b_swz(int k) {
-        if constexpr (F32) return 0;
+        if constexpr (F32 || F64) return 0;
         return (ESZ == 2 ? 4 * (k & 3) : 2 * (k & 7)) & (B_CPR - 1);
     }
     __device__ static void run(const TileProblem &P, int tm, int tn, int split, uint8_t *lds);
@@ -143,8 +163,8 @@ __device__ __forceinline__ void lp2_sources(const TileProblem &P, int m0, int n0
 #pragma unroll
     for (int j = 0; j < Cfg::A_LOADS; ++j) {
         const int t = wave * Cfg::A_LOADS + j;          // 1 KiB piece of the A stage
-        const int r = 16 * t + (lane >> 2);             // tile row
-        const int c = (lane & 3) ^ Cfg::a_swz(r);       // logical chunk held by physical chunk lane&3
+        const int r = (64 / Cfg::A_CPR) * t + lane / Cfg::A_CPR;   // tile row
+        const int c = (lane % Cfg::A_CPR) ^ Cfg::a_swz(r);           // logical chunk at physical chunk lane % A_CPR
         const int row = min(m0 + r, P.m - 1);
         S.ak[j] = c * Cfg::CE;
         S.a[j] = A + ((int64_t)row * P.lda + S.ak[j]) * Cfg::ESZ;
@@ -190,14 +210,15 @@ __device__ __forceinline__ void lp2_issue(const Lp2Src<Cfg> &S, int k0, uint32_t
 }
 
 // MFMA operand fragments of one k-step (KCH consecutive k) for the wave's
-// RB x CB accumulator blocks.  Kind 0: 16-bit, 1: FP8, 2: FP32 (b[t] holds
-// the CB values of MFMA t, one per accumulator block column).
+// RB x CB accumulator blocks.  Kind 0: 16-bit, 1: FP8, 2: FP32, 3: binary64
+// (for the last two, b[t] holds the CB values of MFMA t, one per accumulator
+// block column; binary64 a[rb] holds the lane's four k as two pairs).
 template <int CB> struct Lp2FVec;
 template <> struct Lp2FVec<1> { typedef float T; };
 template <> struct Lp2FVec<2> { typedef f32x2 T; };
 template <> struct Lp2FVec<4> { typedef f32x4 T; };
 
-template <class Cfg, int KIND = (Cfg::MODE == GEMM_MODE_F8E4M3) ? 1 : Cfg::F32 ? 2 : 0>
+template <class Cfg, int KIND = (Cfg::MODE == GEMM_MODE_F8E4M3) ? 1 : Cfg::F32 ? 2 : Cfg::F64 ? 3 : 0>
 struct Lp2Frag;
 template <class Cfg>
 struct Lp2Frag<Cfg, 0> {
@@ -214,6 +235,11 @@ struct Lp2Frag<Cfg, 2> {
     f32x4 a[Cfg::RB];
     typename Lp2FVec<Cfg::CB>::T b[4];
 };
+template <class Cfg>
+struct Lp2Frag<Cfg, 3> {
+    f64x2 a[Cfg::RB][2];
+    typename DVec<Cfg::CB>::T b[4];
+};
 
 // Read piece p of the fragments of k-step kc of the k-tile held in `stage`:
 // p < RB is A row block p, otherwise B column block p - RB (FP32: the B
@@ -227,7 +253,27 @@ __device__ __forceinline__ void lp2_read_piece(const uint8_t *stage, int kc, int
     const int p16 = lane & 15, G = lane >> 4;
     const uint8_t *As = stage;
     const uint8_t *Bs = stage + Cfg::A_STAGE;
-    if constexpr (Cfg::F32) {
+    if constexpr (Cfg::F64) {
+        const int l16 = lane & 15, g4 = lane >> 4;
+        if (p < Cfg::RB) {
+            const int r = wm * Cfg::TM + p * 16 + l16;
+            const uint8_t *row = As + r * Cfg::A_ROWB;
+            F.a[p][0] = *reinterpret_cast<const f64x2 *>(row + 16 * ((2 * g4) ^ Cfg::a_swz(r)));
+            F.a[p][1] = *reinterpret_cast<const f64x2 *>(row + 16 * ((2 * g4 + 1) ^ Cfg::a_swz(r)));
+        } else {
+            const int t = p - Cfg::RB;
+            const double *row = reinterpret_cast<const double *>(Bs + (4 * g4 + t) * Cfg::B_ROWB) + wn * Cfg::TN;
+            if constexpr (Cfg::CB == 4) {
+                const f64x2 lo = *reinterpret_cast<const f64x2 *>(row + 2 * l16);
+                const f64x2 hi = *reinterpret_cast<const f64x2 *>(row + 32 + 2 * l16);
+                F.b[t] = f64x4{lo[0], lo[1], hi[0], hi[1]};
+            } else if constexpr (Cfg::CB == 2) {
+                F.b[t] = *reinterpret_cast<const f64x2 *>(row + 2 * l16);
+            } else {
+                F.b[t] = row[l16];
+            }
+        }
+    } else if constexpr (Cfg::F32) {
         if (p < Cfg::RB) {
             const int r = wm * Cfg::TM + p * 32 + l32;
             F.a[p] = *reinterpret_cast<const f32x4 *>(As + r * Cfg::A_ROWB + 16 * ((2 * kc + g) ^ Cfg::a_swz(r)));
@@ -287,12 +333,18 @@ __device__ __forceinline__ void lp2_read(const uint8_t *stage, int kc, Lp2Frag<C
 }
 
 // MFMA i (0 .. NM-1) of one k-step.  16- and 8-bit: the one MFMA of
-// accumulator block (i / CB, i % CB).  FP32: MFMA t = i / (RB CB) of block
-// ((i / CB) % RB, i % CB), so that consecutive MFMAs feed different
+// accumulator block (i / CB, i % CB).  FP32 and binary64: MFMA t = i / (RB CB)
+// of block ((i / CB) % RB, i % CB), so that consecutive MFMAs feed different
 // accumulators and each block sums t = 0, 1, 2, 3 in order.
 template <class Cfg>
-__device__ __forceinline__ void lp2_mfma1(const Lp2Frag<Cfg> &F, f32x16 (&acc)[Cfg::RB][Cfg::CB], int i) {
-    if constexpr (Cfg::F32) {
+__device__ __forceinline__ void lp2_mfma1(const Lp2Frag<Cfg> &F, typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CB], int i) {
+    if constexpr (Cfg::F64) {
+        const int t = i / (Cfg::RB * Cfg::CB), rb = (i / Cfg::CB) % Cfg::RB, cb = i % Cfg::CB;
+        double bv;
+        if constexpr (Cfg::CB == 1) bv = F.b[t];
+        else bv = F.b[t][cb];
+        acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(F.a[rb][t >> 1][t & 1], bv, acc[rb][cb], 0, 0, 0);
+    } else if constexpr (Cfg::F32) {
         const int t = i / (Cfg::RB * Cfg::CB), rb = (i / Cfg::CB) % Cfg::RB, cb = i % Cfg::CB;
         float bv;
         if constexpr (Cfg::CB == 1) bv = F.b[t];
@@ -358,12 +410,12 @@ __device__ __forceinline__ void lp2_epilogue(float *__restrict__ C, int64_t ldc,
 template <class Cfg, bool BOUNDARY, bool CHECK>
 __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, int u, int kc, uint8_t *lds,
                                          const Lp2Frag<Cfg> &cur, Lp2Frag<Cfg> &nxt,
-                                         f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+                                         typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CB]) {
     constexpr int NP = Cfg::NP;                     // fragment pieces per step
     constexpr int NM = Cfg::NM;                     // MFMAs per step
     if constexpr (BOUNDARY) {
         // MFMAs before the barrier
-        constexpr int H = Cfg::F32 ? NM / 2 : ((Cfg::RB + 1) / 2) * Cfg::CB;
+        constexpr int H = Cfg::FOUR ? NM / 2 : ((Cfg::RB + 1) / 2) * Cfg::CB;
         constexpr int W = NP + Cfg::LOADS;                 // work items after it
         constexpr int PER = (W + (NM - H) - 1) / (NM - H);
 #pragma unroll
@@ -388,7 +440,7 @@ __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, i
     } else {
         const uint8_t *here = lds + u * Cfg::STAGE;
         // FP32 steps have four times the MFMAs: one read after every other one
-        constexpr int SPREAD = Cfg::F32 ? 2 : 1;
+        constexpr int SPREAD = Cfg::FOUR ? 2 : 1;
 #pragma unroll
         for (int t = 0; t < NM; ++t) {
             lp2_mfma1<Cfg>(cur, acc, t);
@@ -404,7 +456,7 @@ __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, i
 // per k-tile) or in `fb` (one step).
 template <class Cfg, bool CHECK>
 __device__ __forceinline__ void lp2_ktile(const Lp2Src<Cfg> &S, int kt0, int i, int u, uint8_t *lds,
-                                          Lp2Frag<Cfg> &fa, Lp2Frag<Cfg> &fb, f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+                                          Lp2Frag<Cfg> &fa, Lp2Frag<Cfg> &fb, typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CB]) {
     if constexpr (Cfg::STEPS == 2) {
         lp2_step<Cfg, false, CHECK>(S, kt0, i, u, 0, lds, fa, fb, acc);
         lp2_step<Cfg, true, CHECK>(S, kt0, i, u, 1, lds, fb, fa, acc);
@@ -418,7 +470,7 @@ __device__ __forceinline__ void lp2_ktile(const Lp2Src<Cfg> &S, int kt0, int i, 
 template <class Cfg, bool CHECK>
 __device__ __forceinline__ void lp2_pair(const Lp2Src<Cfg> &S, int kt0, int i, int u, int nt, bool guard,
                                          uint8_t *lds, Lp2Frag<Cfg> &f0, Lp2Frag<Cfg> &f1,
-                                         f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+                                         typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CB]) {
     if (!guard || i < nt) lp2_ktile<Cfg, CHECK>(S, kt0, i, u, lds, f0, f1, acc);
     if (!guard || i + 1 < nt) {
         if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg, CHECK>(S, kt0, i + 1, u + 1, lds, f0, f1, acc);
@@ -429,7 +481,7 @@ __device__ __forceinline__ void lp2_pair(const Lp2Src<Cfg> &S, int kt0, int i, i
 // One round: the STAGES k-tiles i .. i + STAGES - 1, one per stage, in pairs.
 template <class Cfg, bool CHECK>
 __device__ __forceinline__ void lp2_round(const Lp2Src<Cfg> &S, int kt0, int i, int nt, bool guard, uint8_t *lds,
-                                          Lp2Frag<Cfg> &f0, Lp2Frag<Cfg> &f1, f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+                                          Lp2Frag<Cfg> &f0, Lp2Frag<Cfg> &f1, typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CB]) {
 #pragma unroll
     for (int u = 0; u < Cfg::STAGES; u += 2) lp2_pair<Cfg, CHECK>(S, kt0, i + u, u, nt, guard, lds, f0, f1, acc);
 }
@@ -444,13 +496,14 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
     const int kt1 = min(kt0 + P.kt_per_split, nkt);
     const int nt = max(0, kt1 - kt0);
 
-    f32x16 acc[Cfg::RB][Cfg::CB];
+    typename Cfg::Acc acc[Cfg::RB][Cfg::CB];
+    constexpr int NACC = sizeof(typename Cfg::Acc) / (Cfg::F64 ? 8 : 4);
 #pragma unroll
     for (int rb = 0; rb < Cfg::RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < Cfg::CB; ++cb)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[rb][cb][r] = 0.f;
+            for (int r = 0; r < NACC; ++r) acc[rb][cb][r] = 0;
 
     if (nt > 0) {
         // Fill the ring with k-tiles 0 .. STAGES-1 (those past kt1 read the
@@ -476,12 +529,17 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
         wait_vmcnt<0>();   // the loads past the end have landed before the ring is reused
     }
     __syncthreads();       // the LDS ring may be refilled by this workgroup's next tile
-    float *C;
-    int64_t ldc;
-    float scale;
-    epilogue_target(P, split, C, ldc, scale);
-    if constexpr (Cfg::F32) tile_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
-    else lp2_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
+    if constexpr (Cfg::F64) {
+        // binary64 products have no split-K; P.C holds double elements
+        f64_epilogue<Cfg>(reinterpret_cast<double *>(P.C), P.ldc, P.m, P.n, m0, n0, acc);
+    } else {
+        float *C;
+        int64_t ldc;
+        float scale;
+        epilogue_target(P, split, C, ldc, scale);
+        if constexpr (Cfg::F32) tile_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
+        else lp2_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
+    }
 }
 
 template <int MODE, int BM, int BN, int STAGES, int WM, int WN>

@@ -120,6 +120,58 @@ def test_f64_strided_misaligned_and_guard_band():
         assert np.isnan(full[mask]).all(), f"cfg {cfg} wrote outside C"
 
 
+# k and n even (whole 16-byte chunks): the asynchronous-copy tiles run these;
+# ragged m and n, a partial k-tile of 16, one row and one chunk
+F64_CHUNKED = [(1, 2, 2), (33, 34, 18), (64, 512, 16), (129, 66, 18), (257, 130, 1034), (300, 208, 1040),
+               (513, 260, 4098)]
+
+
+def _f64_async_configs():
+    return [c for c in range(mg.num_configs(mg.MODE_F64)) if mg.config_info(mg.MODE_F64, c)["lds_bytes"] >= 131072]
+
+
+@pytest.mark.parametrize("m,n,k", F64_CHUNKED)
+def test_f64_async_tiles_chunked_shapes(m, n, k):
+    """The asynchronous-copy binary64 tiles: within the bound of the
+    compensated oracle and bit for bit equal to the register-staged tile
+    (the same MFMAs in the same k order)."""
+    log(f"f64 async tiles {(m, n, k)}")
+    A, B = synth.pair64(m, n, k, seed=m + 7 * n + 3 * k)
+    R = oracle.gemm_dot2(A, B)
+    dA, dB = dev(A), dev(B)
+    ref = host(mg.gemm_f64(dA, dB, cfg=0))
+    cfgs = _f64_async_configs()
+    assert cfgs
+    for cfg in cfgs:
+        C = host(mg.gemm_f64(dA, dB, cfg=cfg))
+        _assert_f64(C, R, A, B, k, f"f64 async {(m, n, k)} cfg {cfg}")
+        assert np.array_equal(C, ref), cfg
+
+
+def test_f64_async_tiles_strides_and_fallback():
+    """Even padded strides run the asynchronous-copy tiles; an odd stride or a
+    base 8 bytes off 16-byte alignment falls back to the register-staged
+    tile.  Same bits in every case, nothing written outside C."""
+    log("f64 async tiles strides/fallback")
+    m, n, k = 140, 98, 260
+    A, B = synth.pair64(m, n, k, seed=45)
+    ref = host(mg.gemm_f64(dev(A), dev(B), cfg=0))
+    for pad_a, pad_b, off in [(2, 4, 0), (1, 2, 0), (2, 4, 1)]:
+        bufA = torch.zeros((m, k + pad_a + off), dtype=torch.float64, device="cuda")
+        bufB = torch.zeros((k, n + pad_b + off), dtype=torch.float64, device="cuda")
+        dA, dB = bufA[:, off:off + k], bufB[:, off:off + n]
+        dA.copy_(dev(A))
+        dB.copy_(dev(B))
+        for cfg in _f64_async_configs():
+            big = torch.full((m + 2, n + 2), float("nan"), dtype=torch.float64, device="cuda")
+            mg.gemm_f64(dA, dB, out=big[1:m + 1, 1:n + 1], cfg=cfg)
+            h = host(big)
+            assert np.array_equal(h[1:m + 1, 1:n + 1], ref), (pad_a, pad_b, off, cfg)
+            mask = np.ones_like(h, dtype=bool)
+            mask[1:m + 1, 1:n + 1] = False
+            assert np.isnan(h[mask]).all()
+
+
 def test_f64_empty_and_k0():
     log("f64 empty / k = 0")
     C = torch.full((5, 6), 7.0, dtype=torch.float64, device="cuda")
