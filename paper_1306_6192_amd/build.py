@@ -2,12 +2,16 @@
 
 Every source under ``csrc/`` (HIP kernels and the C++ host runtime) is
 compiled for gfx950 only and linked into one shared library that exports the
-C-ABI declared in ``include/mi355gemm.h``.
+C-ABI declared in ``include/mi355gemm.h``.  The compiler's per-kernel
+resource report (registers, scratch, occupancy, LDS) is kept in
+``_build/kernel_resources.txt``; a kernel that spills registers to scratch
+memory fails the build, since every tile is sized to fit its register budget.
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -31,9 +35,27 @@ def sources():
                   if f.endswith(".hip") or f.endswith(".cpp"))
 
 
-def _compile(src: str, verbose: bool) -> str:
+_REMARK = re.compile(r"remark:\s+(Function Name|ScratchSize \[bytes/lane\]|VGPRs|AGPRs|VGPRs Spill|"
+                     r"Occupancy \[waves/SIMD\]|LDS Size \[bytes/block\]):\s+(\S+)")
+
+
+def _resources(stderr: str) -> list:
+    """(kernel, {field: value}) from the kernel-resource-usage remarks."""
+    out = []
+    for ln in stderr.splitlines():
+        m = _REMARK.search(ln)
+        if not m:
+            continue
+        if m.group(1) == "Function Name":
+            out.append((m.group(2), {}))
+        elif out:
+            out[-1][1][m.group(1)] = m.group(2)
+    return out
+
+
+def _compile(src: str, verbose: bool):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, "-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     if verbose:
@@ -44,7 +66,7 @@ def _compile(src: str, verbose: bool) -> str:
     warn = [ln for ln in r.stderr.splitlines() if "warning" in ln and "packed-fp32-ops" not in ln]
     if warn and verbose:
         print("\n".join(warn), file=sys.stderr)
-    return obj
+    return obj, _resources(r.stderr)
 
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
@@ -52,7 +74,16 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        done = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    objs = [o for o, _ in done]
+    kernels = sorted({k: v for _, res in done for k, v in res}.items())
+    with open(os.path.join(BUILD, "kernel_resources.txt"), "w") as f:
+        for k, v in kernels:
+            f.write(k + "  " + "  ".join(f"{a}={b}" for a, b in sorted(v.items())) + "\n")
+    spills = [k for k, v in kernels
+              if v.get("ScratchSize [bytes/lane]", "0") != "0" or v.get("VGPRs Spill", "0") != "0"]
+    if spills:
+        raise RuntimeError("kernels spill registers to scratch memory: " + ", ".join(spills))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:

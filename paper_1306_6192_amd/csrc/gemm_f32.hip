@@ -23,8 +23,8 @@ static const KernelCfg kF32Configs[] = {
     // asynchronous-copy tiles (four-stage LDS ring, k-tiles of 16): eight
     // waves (two per SIMD) at 2 x 4 and 4 x 2, four waves with 128 x 128
     // per wave (one per SIMD, accumulators in AGPRs), eight waves on
-    // 128 x 256, four waves on 128 x 128 (two workgroups per CU), four waves
-    // on 256 x 128 and 128 x 256
+    // 128 x 256, four waves on 128 x 128, four waves on 256 x 128 and
+    // 128 x 256
     make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 256, 4, 2, 4>, 2, 4>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 256, 4, 4, 2>, 2, 4>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 256, 4>, 1, 4>(),

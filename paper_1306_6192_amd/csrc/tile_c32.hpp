@@ -161,10 +161,11 @@ __device__ __forceinline__ void c32_compute_stage(const float *stage, f32x16 (&r
     }
 }
 
-template <class Cfg>
-__device__ __forceinline__ void c32_epilogue(float *__restrict__ C, int64_t ldc, int M, int N, int m0, int n0,
-                                             const f32x16 (&re)[Cfg::RB][Cfg::CB],
-                                             const f32x16 (&im)[Cfg::RB][Cfg::CB]) {
+// Store the wave's complex accumulators to C: re(rb, cb, r) and im(rb, cb, r)
+// give register r of the real and imaginary 32x32 blocks (rb, cb).
+template <class Cfg, class Re, class Im>
+__device__ __forceinline__ void c32_store(float *__restrict__ C, int64_t ldc, int M, int N, int m0, int n0, Re re,
+                                          Im im) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
@@ -180,8 +181,8 @@ __device__ __forceinline__ void c32_epilogue(float *__restrict__ C, int64_t ldc,
             float v[2 * Cfg::CB];
 #pragma unroll
             for (int cb = 0; cb < Cfg::CB; ++cb) {
-                v[2 * cb] = re[rb][cb][r];
-                v[2 * cb + 1] = im[rb][cb][r];
+                v[2 * cb] = re(rb, cb, r);
+                v[2 * cb + 1] = im(rb, cb, r);
             }
             float *p = C + 2 * ((int64_t)row * ldc + col);
             if (full_cols) {
@@ -196,6 +197,14 @@ __device__ __forceinline__ void c32_epilogue(float *__restrict__ C, int64_t ldc,
             }
         }
     }
+}
+
+template <class Cfg>
+__device__ __forceinline__ void c32_epilogue(float *__restrict__ C, int64_t ldc, int M, int N, int m0, int n0,
+                                             const f32x16 (&re)[Cfg::RB][Cfg::CB],
+                                             const f32x16 (&im)[Cfg::RB][Cfg::CB]) {
+    c32_store<Cfg>(C, ldc, M, N, m0, n0, [&](int rb, int cb, int r) { return re[rb][cb][r]; },
+                   [&](int rb, int cb, int r) { return im[rb][cb][r]; });
 }
 
 template <class Cfg>

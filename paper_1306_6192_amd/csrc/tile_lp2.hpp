@@ -1,9 +1,10 @@
-// Asynchronous-copy output tile (BF16, F16, FP8, FP32 and binary64).
+// Asynchronous-copy output tile (BF16, F16, FP8, FP32, binary64 and complex
+// float).
 //
 // Same arithmetic as the register-staged tiles (tile_lp.hpp for BF16, F16
-// and FP8, tile_f32.hpp for FP32, tile_f64.hpp for binary64: same MFMA
-// instructions, same k order, so each pair produces identical bits),
-// different data movement:
+// and FP8, tile_f32.hpp for FP32, tile_f64.hpp for binary64, tile_c32.hpp
+// for complex float: same MFMA instructions, same k order, so each pair
+// produces identical bits), different data movement:
 //   * A and B go from HBM straight into LDS with 16-byte direct loads
 //     (global_load_lds_dwordx4): no staging registers and no register
 //     transpose; lane L of one such load lands at LDS base + 16*L.
@@ -20,6 +21,13 @@
 //     one step per k-tile: lane (l%16, g = l/16) reads doubles 4g .. 4g + 3
 //     of its row as two 16-byte chunks, and MFMA t = 0..3 takes k = 4g + t;
 //     B row 4g + t is read at the column pairs 32h + 2(l%16) of tile_f64.hpp.
+//   * complex float (interleaved (re, im) pairs, four real 32x32x2 MFMAs per
+//     complex term): A rows of a k-tile are 128 bytes (16 complex, the
+//     register-staged tile's k-tile), two steps of 8 k; lane (l%32, g =
+//     l/32) reads complex k = 8c + 4g .. + 3 of its row as two 16-byte
+//     chunks and B row 8c + 4g + t at complex column CB*(l%32); the real and
+//     imaginary parts of block cb accumulate in acc[rb][2cb] and
+//     acc[rb][2cb + 1].
 //   * 16- and 8-bit B stays row-major (k x n) in LDS; the MFMA B operand
 //     (consecutive k of one column per lane) is gathered with the transposing
 //     LDS reads
@@ -42,6 +50,7 @@
 
 #include <type_traits>
 
+#include "tile_c32.hpp"
 #include "tile_common.hpp"
 #include "tile_f64.hpp"
 
@@ -71,23 +80,25 @@ struct Lp2Cfg {
     static constexpr int THREADS = 64 * WAVES;
     static constexpr bool F32 = (MODE == GEMM_MODE_F32);
     static constexpr bool F64 = (MODE == GEMM_MODE_F64);
+    static constexpr bool C32 = (MODE == GEMM_MODE_C32);
     static constexpr int BLK = F64 ? 16 : 32;           // accumulator block edge
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int RB = TM / BLK, CB = TN / BLK;
-    static constexpr int ESZ = (MODE == GEMM_MODE_F8E4M3) ? 1 : F64 ? 8 : F32 ? 4 : 2;
+    static constexpr int CBA = C32 ? 2 * CB : CB;       // accumulator blocks per row block
+    static constexpr int ESZ = (MODE == GEMM_MODE_F8E4M3) ? 1 : (F64 || C32) ? 8 : F32 ? 4 : 2;
     static constexpr int CE = 16 / ESZ;                 // elements per 16-byte chunk
-    static constexpr int A_ROWB = F64 ? 128 : 64;       // bytes of an A row per k-tile
+    static constexpr int A_ROWB = (F64 || C32) ? 128 : 64;   // bytes of an A row per k-tile
     static constexpr int A_CPR = A_ROWB / 16;           // 16-byte chunks per A row
     static constexpr int BK = A_ROWB / ESZ;             // k per k-tile
     // k per step: one MFMA (16- and 8-bit), four 32x32x2 MFMAs (FP32), four
-    // 16x16x4 MFMAs (binary64)
-    static constexpr int KCH = (MODE == GEMM_MODE_F8E4M3) ? 64 : F64 ? 16 : F32 ? 8 : 16;
-    static constexpr int MFMA_K = F32 ? 2 : F64 ? 4 : KCH;
+    // 16x16x4 MFMAs (binary64), four times four 32x32x2 MFMAs (complex)
+    static constexpr int KCH = (MODE == GEMM_MODE_F8E4M3) ? 64 : F64 ? 16 : (F32 || C32) ? 8 : 16;
+    static constexpr int MFMA_K = (F32 || C32) ? 2 : F64 ? 4 : KCH;
     static constexpr int STEPS = BK / KCH;
-    static constexpr bool FOUR = F32 || F64;            // four MFMAs per block per step
+    static constexpr bool FOUR = F32 || F64 || C32;     // four k-slots per block per step
     static constexpr int NPB = FOUR ? 4 : CB;           // B fragment reads per step
     static constexpr int NP = RB + NPB;                 // fragment reads per step
-    static constexpr int NM = RB * CB * (FOUR ? 4 : 1); // MFMAs per step
+    static constexpr int NM = RB * CB * (FOUR ? 4 : 1) * (C32 ? 4 : 1);   // MFMAs per step
     typedef typename std::conditional<F64, f64x4, f32x16>::type Acc;
     static constexpr int B_ROWB = BN * ESZ;
     static constexpr int B_CPR = B_ROWB / 16;           // 16-byte chunks per B row
@@ -116,7 +127,7 @@ struct Lp2Cfg {
         return ((r >> 1) ^ (r >> 2)) & 3;
     }
     __device__ static __forceinline__ int b_swz(int k) {
-        if constexpr (F32 || F64) return 0;
+        if constexpr (F32 || F64 || C32) return 0;
         return (ESZ == 2 ? 4 * (k & 3) : 2 * (k & 7)) & (B_CPR - 1);
     }
     __device__ static void run(const TileProblem &P, int tm, int tn, int split, uint8_t *lds);
@@ -210,15 +221,17 @@ __device__ __forceinline__ void lp2_issue(const Lp2Src<Cfg> &S, int k0, uint32_t
 }
 
 // MFMA operand fragments of one k-step (KCH consecutive k) for the wave's
-// RB x CB accumulator blocks.  Kind 0: 16-bit, 1: FP8, 2: FP32, 3: binary64
-// (for the last two, b[t] holds the CB values of MFMA t, one per accumulator
-// block column; binary64 a[rb] holds the lane's four k as two pairs).
+// RB x CB accumulator blocks.  Kind 0: 16-bit, 1: FP8, 2: FP32, 3: binary64,
+// 4: complex float (for the last three, b[t] holds the CB values of MFMA
+// slot t, one per accumulator block column; binary64 and complex a[rb] hold
+// the lane's four k as two 16-byte chunks).
 template <int CB> struct Lp2FVec;
 template <> struct Lp2FVec<1> { typedef float T; };
 template <> struct Lp2FVec<2> { typedef f32x2 T; };
 template <> struct Lp2FVec<4> { typedef f32x4 T; };
 
-template <class Cfg, int KIND = (Cfg::MODE == GEMM_MODE_F8E4M3) ? 1 : Cfg::F32 ? 2 : Cfg::F64 ? 3 : 0>
+template <class Cfg,
+          int KIND = (Cfg::MODE == GEMM_MODE_F8E4M3) ? 1 : Cfg::F32 ? 2 : Cfg::F64 ? 3 : Cfg::C32 ? 4 : 0>
 struct Lp2Frag;
 template <class Cfg>
 struct Lp2Frag<Cfg, 0> {
@@ -240,6 +253,11 @@ struct Lp2Frag<Cfg, 3> {
     f64x2 a[Cfg::RB][2];
     typename DVec<Cfg::CB>::T b[4];
 };
+template <class Cfg>
+struct Lp2Frag<Cfg, 4> {
+    f32x4 a[Cfg::RB][2];                        // four complex k: (re, im) x 2, twice
+    typename Lp2FVec<2 * Cfg::CB>::T b[4];      // CB complex values of MFMA slot t
+};
 
 // Read piece p of the fragments of k-step kc of the k-tile held in `stage`:
 // p < RB is A row block p, otherwise B column block p - RB (FP32: the B
@@ -253,7 +271,19 @@ __device__ __forceinline__ void lp2_read_piece(const uint8_t *stage, int kc, int
     const int p16 = lane & 15, G = lane >> 4;
     const uint8_t *As = stage;
     const uint8_t *Bs = stage + Cfg::A_STAGE;
-    if constexpr (Cfg::F64) {
+    if constexpr (Cfg::C32) {
+        if (p < Cfg::RB) {
+            const int r = wm * Cfg::TM + p * 32 + l32;
+            const uint8_t *row = As + r * Cfg::A_ROWB;
+            F.a[p][0] = *reinterpret_cast<const f32x4 *>(row + 16 * ((4 * kc + 2 * g) ^ Cfg::a_swz(r)));
+            F.a[p][1] = *reinterpret_cast<const f32x4 *>(row + 16 * ((4 * kc + 2 * g + 1) ^ Cfg::a_swz(r)));
+        } else {
+            const int t = p - Cfg::RB;
+            const float *row = reinterpret_cast<const float *>(Bs + (8 * kc + 4 * g + t) * Cfg::B_ROWB);
+            F.b[t] = *reinterpret_cast<const typename Lp2FVec<2 * Cfg::CB>::T *>(
+                row + 2 * (wn * Cfg::TN + Cfg::CB * l32));
+        }
+    } else if constexpr (Cfg::F64) {
         const int l16 = lane & 15, g4 = lane >> 4;
         if (p < Cfg::RB) {
             const int r = wm * Cfg::TM + p * 16 + l16;
@@ -337,8 +367,27 @@ __device__ __forceinline__ void lp2_read(const uint8_t *stage, int kc, Lp2Frag<C
 // of block ((i / CB) % RB, i % CB), so that consecutive MFMAs feed different
 // accumulators and each block sums t = 0, 1, 2, 3 in order.
 template <class Cfg>
-__device__ __forceinline__ void lp2_mfma1(const Lp2Frag<Cfg> &F, typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CB], int i) {
-    if constexpr (Cfg::F64) {
+__device__ __forceinline__ void lp2_mfma1(const Lp2Frag<Cfg> &F, typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CBA], int i) {
+    if constexpr (Cfg::C32) {
+        // slot t, then product j = 0..3 (Re += ar br, Re += (-ai) bi,
+        // Im += ar bi, Im += ai br), then the blocks: each accumulator still
+        // receives its products in the register-staged tile's order
+        constexpr int NB = Cfg::RB * Cfg::CB;
+        const int t = i / (4 * NB), j = (i / NB) % 4, rb = (i / Cfg::CB) % Cfg::RB, cb = i % Cfg::CB;
+        const float ar = F.a[rb][t >> 1][2 * (t & 1)], ai = F.a[rb][t >> 1][2 * (t & 1) + 1];
+        float br, bi;
+        if constexpr (Cfg::CB == 1) {
+            br = F.b[t][0];
+            bi = F.b[t][1];
+        } else {
+            br = F.b[t][2 * cb];
+            bi = F.b[t][2 * cb + 1];
+        }
+        if (j == 0) acc[rb][2 * cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, acc[rb][2 * cb], 0, 0, 0);
+        else if (j == 1) acc[rb][2 * cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, acc[rb][2 * cb], 0, 0, 0);
+        else if (j == 2) acc[rb][2 * cb + 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, acc[rb][2 * cb + 1], 0, 0, 0);
+        else acc[rb][2 * cb + 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, acc[rb][2 * cb + 1], 0, 0, 0);
+    } else if constexpr (Cfg::F64) {
         const int t = i / (Cfg::RB * Cfg::CB), rb = (i / Cfg::CB) % Cfg::RB, cb = i % Cfg::CB;
         double bv;
         if constexpr (Cfg::CB == 1) bv = F.b[t];
@@ -410,7 +459,7 @@ __device__ __forceinline__ void lp2_epilogue(float *__restrict__ C, int64_t ldc,
 template <class Cfg, bool BOUNDARY, bool CHECK>
 __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, int u, int kc, uint8_t *lds,
                                          const Lp2Frag<Cfg> &cur, Lp2Frag<Cfg> &nxt,
-                                         typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CB]) {
+                                         typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CBA]) {
     constexpr int NP = Cfg::NP;                     // fragment pieces per step
     constexpr int NM = Cfg::NM;                     // MFMAs per step
     if constexpr (BOUNDARY) {
@@ -418,6 +467,7 @@ __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, i
         constexpr int H = Cfg::FOUR ? NM / 2 : ((Cfg::RB + 1) / 2) * Cfg::CB;
         constexpr int W = NP + Cfg::LOADS;                 // work items after it
         constexpr int PER = (W + (NM - H) - 1) / (NM - H);
+        static_assert(H < NM && (NM - H) * PER >= W, "every read and refill load is issued");
 #pragma unroll
         for (int t = 0; t < H; ++t) lp2_mfma1<Cfg>(cur, acc, t);
         __builtin_amdgcn_sched_barrier(0);
@@ -439,13 +489,22 @@ __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, i
         }
     } else {
         const uint8_t *here = lds + u * Cfg::STAGE;
-        // FP32 steps have four times the MFMAs: one read after every other one
-        constexpr int SPREAD = Cfg::FOUR ? 2 : 1;
+        // the NP reads of the next step go after the MFMAs, PER at a time:
+        // after every other MFMA where a step has at least twice as many
+        // MFMAs as reads (the FP32, binary64 and complex tiles), otherwise
+        // after every MFMA
+        constexpr int SPREAD = (Cfg::FOUR && NM >= 2 * NP) ? 2 : 1;
+        constexpr int PER = (NP + NM / SPREAD - 1) / (NM / SPREAD);
+        static_assert((NM / SPREAD) * PER >= NP, "every fragment piece of the next step is read");
 #pragma unroll
         for (int t = 0; t < NM; ++t) {
             lp2_mfma1<Cfg>(cur, acc, t);
             __builtin_amdgcn_sched_barrier(0);
-            if (t % SPREAD == 0 && t / SPREAD < NP) lp2_read_piece<Cfg>(here, kc + 1, t / SPREAD, nxt);
+            if (t % SPREAD == 0) {
+#pragma unroll
+                for (int w = (t / SPREAD) * PER; w < (t / SPREAD + 1) * PER && w < NP; ++w)
+                    lp2_read_piece<Cfg>(here, kc + 1, w, nxt);
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -456,7 +515,7 @@ __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, i
 // per k-tile) or in `fb` (one step).
 template <class Cfg, bool CHECK>
 __device__ __forceinline__ void lp2_ktile(const Lp2Src<Cfg> &S, int kt0, int i, int u, uint8_t *lds,
-                                          Lp2Frag<Cfg> &fa, Lp2Frag<Cfg> &fb, typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CB]) {
+                                          Lp2Frag<Cfg> &fa, Lp2Frag<Cfg> &fb, typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CBA]) {
     if constexpr (Cfg::STEPS == 2) {
         lp2_step<Cfg, false, CHECK>(S, kt0, i, u, 0, lds, fa, fb, acc);
         lp2_step<Cfg, true, CHECK>(S, kt0, i, u, 1, lds, fb, fa, acc);
@@ -470,20 +529,12 @@ __device__ __forceinline__ void lp2_ktile(const Lp2Src<Cfg> &S, int kt0, int i, 
 template <class Cfg, bool CHECK>
 __device__ __forceinline__ void lp2_pair(const Lp2Src<Cfg> &S, int kt0, int i, int u, int nt, bool guard,
                                          uint8_t *lds, Lp2Frag<Cfg> &f0, Lp2Frag<Cfg> &f1,
-                                         typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CB]) {
+                                         typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CBA]) {
     if (!guard || i < nt) lp2_ktile<Cfg, CHECK>(S, kt0, i, u, lds, f0, f1, acc);
     if (!guard || i + 1 < nt) {
         if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg, CHECK>(S, kt0, i + 1, u + 1, lds, f0, f1, acc);
         else lp2_ktile<Cfg, CHECK>(S, kt0, i + 1, u + 1, lds, f1, f0, acc);
     }
-}
-
-// One round: the STAGES k-tiles i .. i + STAGES - 1, one per stage, in pairs.
-template <class Cfg, bool CHECK>
-__device__ __forceinline__ void lp2_round(const Lp2Src<Cfg> &S, int kt0, int i, int nt, bool guard, uint8_t *lds,
-                                          Lp2Frag<Cfg> &f0, Lp2Frag<Cfg> &f1, typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CB]) {
-#pragma unroll
-    for (int u = 0; u < Cfg::STAGES; u += 2) lp2_pair<Cfg, CHECK>(S, kt0, i + u, u, nt, guard, lds, f0, f1, acc);
 }
 
 template <class Cfg>
@@ -496,12 +547,12 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
     const int kt1 = min(kt0 + P.kt_per_split, nkt);
     const int nt = max(0, kt1 - kt0);
 
-    typename Cfg::Acc acc[Cfg::RB][Cfg::CB];
+    typename Cfg::Acc acc[Cfg::RB][Cfg::CBA];
     constexpr int NACC = sizeof(typename Cfg::Acc) / (Cfg::F64 ? 8 : 4);
 #pragma unroll
     for (int rb = 0; rb < Cfg::RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < Cfg::CB; ++cb)
+        for (int cb = 0; cb < Cfg::CBA; ++cb)
 #pragma unroll
             for (int r = 0; r < NACC; ++r) acc[rb][cb][r] = 0;
 
@@ -522,16 +573,31 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
         int i = 0;
         // rounds whose refills (k-tiles i + STAGES .. i + 2 STAGES - 1) are
         // whole: no k bound on the loads
-        for (; i + 2 * Cfg::STAGES <= nfull; i += Cfg::STAGES) lp2_round<Cfg, false>(S, kt0, i, nt, false, lds, f0, f1, acc);
-        for (; i + Cfg::STAGES <= nt; i += Cfg::STAGES) lp2_round<Cfg, true>(S, kt0, i, nt, false, lds, f0, f1, acc);
+        // (the stage loops are written out here: behind a helper function
+        // the compiler unrolls them less and the eight-wave FP32 tiles spill)
+        for (; i + 2 * Cfg::STAGES <= nfull; i += Cfg::STAGES) {
+#pragma unroll
+            for (int u = 0; u < Cfg::STAGES; u += 2)
+                lp2_pair<Cfg, false>(S, kt0, i + u, u, nt, false, lds, f0, f1, acc);
+        }
+        for (; i + Cfg::STAGES <= nt; i += Cfg::STAGES) {
+#pragma unroll
+            for (int u = 0; u < Cfg::STAGES; u += 2)
+                lp2_pair<Cfg, true>(S, kt0, i + u, u, nt, false, lds, f0, f1, acc);
+        }
         // the last nt mod STAGES k-tiles (stages 0 ..)
-        lp2_round<Cfg, true>(S, kt0, i, nt, true, lds, f0, f1, acc);
+#pragma unroll
+        for (int u = 0; u < Cfg::STAGES; u += 2) lp2_pair<Cfg, true>(S, kt0, i + u, u, nt, true, lds, f0, f1, acc);
         wait_vmcnt<0>();   // the loads past the end have landed before the ring is reused
     }
     __syncthreads();       // the LDS ring may be refilled by this workgroup's next tile
     if constexpr (Cfg::F64) {
         // binary64 products have no split-K; P.C holds double elements
         f64_epilogue<Cfg>(reinterpret_cast<double *>(P.C), P.ldc, P.m, P.n, m0, n0, acc);
+    } else if constexpr (Cfg::C32) {
+        // nor do complex ones; P.C holds interleaved complex elements
+        c32_store<Cfg>(P.C, P.ldc, P.m, P.n, m0, n0, [&](int rb, int cb, int r) { return acc[rb][2 * cb][r]; },
+                       [&](int rb, int cb, int r) { return acc[rb][2 * cb + 1][r]; });
     } else {
         float *C;
         int64_t ldc;

@@ -46,16 +46,17 @@ void heuristic_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg_out, i
     for (int c = 0; c < count; ++c) {
         const KernelCfg &kc = t[c];
         // chunked (asynchronous-copy) tiles need k and n in whole 16-byte
-        // chunks; where they apply they sustain 1.4x (16-bit) to 3.5x (FP8)
-        // and 1.1x (FP32, binary64) the register-staged tile's rate at 8192^3
-        // (measured)
+        // chunks; where they apply they sustain 1.4x (16-bit) to 3.5x (FP8),
+        // 1.1x (FP32) and 1.15-1.2x (binary64, complex) the register-staged
+        // tile's rate at 8192^3 (measured; the complex 128x128 one beats the
+        // register-staged 256x128 one although tile_eff favours the latter)
         if (kc.chunk && (k % kc.chunk || n % kc.chunk)) continue;
         if (kc.presplit && n % 8) continue;
         // the pre-split split-BF16x3 path runs at about 1.75x the register-
         // staged split tile at 8192^3 (its operands are split once, not once
         // per output tile)
-        const double bonus =
-            kc.chunk ? (mode == GEMM_MODE_F32 || mode == GEMM_MODE_F64 ? 1.1 : 1.7) : (kc.presplit ? 1.75 : 1.0);
+        double bonus = kc.presplit ? 1.75 : 1.0;
+        if (kc.chunk) bonus = mode == GEMM_MODE_F32 ? 1.1 : (mode == GEMM_MODE_F64 || mode == GEMM_MODE_C32) ? 1.15 : 1.7;
         const int64_t tiles = ((m + kc.bm - 1) / kc.bm) * ((n + kc.bn - 1) / kc.bn);
         const int64_t nkt = (k + split_grain(mode) - 1) / split_grain(mode) * (split_grain(mode) / kc.bk);
         // the binary64 and complex families have no split-K

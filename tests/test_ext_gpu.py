@@ -262,6 +262,57 @@ def test_c32_strided_misaligned_and_guard_band():
         assert np.isnan(full[mask].real).all() and np.isnan(full[mask].imag).all(), cfg
 
 
+# k and n even (whole 16-byte chunks of two complex values): the
+# asynchronous-copy tiles run these
+C32_CHUNKED = [(1, 2, 2), (33, 34, 18), (64, 256, 16), (129, 66, 26), (257, 130, 1034), (300, 208, 1040)]
+
+
+def _c32_async_configs():
+    return [c for c in range(mg.num_configs(mg.MODE_C32)) if mg.config_info(mg.MODE_C32, c)["lds_bytes"] >= 131072]
+
+
+@pytest.mark.parametrize("m,n,k", C32_CHUNKED)
+def test_c32_async_tiles_chunked_shapes(m, n, k):
+    """The asynchronous-copy complex tiles: within the component bound of the
+    binary64 complex oracle and bit for bit equal to the register-staged tile
+    (each accumulator receives the same real products in the same order)."""
+    log(f"c32 async tiles {(m, n, k)}")
+    A, B = synth.pair_c64(m, n, k, seed=m + 3 * n + 7 * k)
+    R = oracle.gemm_c128(A, B)
+    dA, dB = dev(A), dev(B)
+    ref = host(mg.gemm_c32(dA, dB, cfg=0))
+    cfgs = _c32_async_configs()
+    assert cfgs
+    for cfg in cfgs:
+        C = host(mg.gemm_c32(dA, dB, cfg=cfg))
+        _assert_c32(C, R, A, B, k, f"c32 async {(m, n, k)} cfg {cfg}")
+        assert np.array_equal(C.view(np.float32), ref.view(np.float32)), cfg
+
+
+def test_c32_async_tiles_strides_and_fallback():
+    """Even padded strides run the asynchronous-copy tiles; an odd stride or a
+    base one complex element off 16-byte alignment falls back to the
+    register-staged tile.  Same bits, nothing written outside C."""
+    log("c32 async tiles strides/fallback")
+    m, n, k = 140, 98, 260
+    A, B = synth.pair_c64(m, n, k, seed=48)
+    ref = host(mg.gemm_c32(dev(A), dev(B), cfg=0))
+    for pad_a, pad_b, off in [(2, 4, 0), (1, 2, 0), (2, 4, 1)]:
+        bufA = torch.zeros((m, k + pad_a + off), dtype=torch.complex64, device="cuda")
+        bufB = torch.zeros((k, n + pad_b + off), dtype=torch.complex64, device="cuda")
+        dA, dB = bufA[:, off:off + k], bufB[:, off:off + n]
+        dA.copy_(dev(A))
+        dB.copy_(dev(B))
+        for cfg in _c32_async_configs():
+            big = torch.full((m + 2, n + 2), complex("nan+nanj"), dtype=torch.complex64, device="cuda")
+            mg.gemm_c32(dA, dB, out=big[1:m + 1, 1:n + 1], cfg=cfg)
+            h = host(big)
+            assert np.array_equal(h[1:m + 1, 1:n + 1].view(np.float32), ref.view(np.float32)), (pad_a, pad_b, off, cfg)
+            mask = np.ones(h.shape, dtype=bool)
+            mask[1:m + 1, 1:n + 1] = False
+            assert np.isnan(h[mask].real).all() and np.isnan(h[mask].imag).all()
+
+
 def test_c32_empty_and_k0():
     log("c32 k = 0")
     C = torch.full((5, 6), 7 + 7j, dtype=torch.complex64, device="cuda")
