@@ -32,6 +32,9 @@ static const KernelCfg kF32Configs[] = {
     make_cfg<Lp2Cfg<GEMM_MODE_F32, 128, 128, 4>, 2, 4>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 128, 4>, 1, 4>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F32, 128, 256, 4>, 1, 4>(),
+    // register-staged k-tiles of 16 (half the LDS): three workgroups per CU
+    make_cfg<F32Cfg<128, 128, 2, 2, 16>, 3>(),
+    make_cfg<F32Cfg<64, 64, 2, 2, 16>, 3>(),
 };
 
 const KernelCfg *f32_configs(int *count) {
@@ -40,6 +43,6 @@ const KernelCfg *f32_configs(int *count) {
 }
 
 static const GroupedKernel kF32Grouped = {
-    {3, 6}, 2, launch_grouped_t<F32Cfg<128, 128>, F32Cfg<64, 64>, 2>};
+    {18, 19}, 3, launch_grouped_t<F32Cfg<128, 128, 2, 2, 16>, F32Cfg<64, 64, 2, 2, 16>, 3>};
 
 const GroupedKernel *f32_grouped() { return &kF32Grouped; }

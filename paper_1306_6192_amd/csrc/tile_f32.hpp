@@ -2,7 +2,8 @@
 //
 // One workgroup of WM x WN waves (default 2 x 2, 256 lanes) owns a BM x BN
 // tile of C and walks
-// the k dimension in k-tiles of BK = 32:
+// the k dimension in k-tiles of BK = 32 (or 16, half the LDS, for more
+// resident workgroups):
 //   HBM/L2 -> registers (16-B loads, masked at the edges)
 //          -> LDS (two stages, rows padded against bank conflicts)
 //          -> MFMA fragments -> float32 accumulators in AGPRs/VGPRs.
@@ -31,9 +32,14 @@
 
 #include "tile_common.hpp"
 
-template <int BM_, int BN_, int WM_ = 2, int WN_ = 2>
+template <int BM_, int BN_, int WM_ = 2, int WN_ = 2, int BK_ = 32>
 struct F32Cfg {
-    static constexpr int BM = BM_, BN = BN_, BK = 32;
+    static constexpr int BM = BM_, BN = BN_, BK = BK_;
+    static_assert(BK == 16 || BK == 32, "k-tiles of whole 8-k chunks, at most 32");
+    // The unmasked copy of the k-loop for interior tiles costs registers; the
+    // k-tile-16 tiles exist for three workgroups per CU (168 VGPRs), so they
+    // run the masked loop only (same arithmetic either way).
+    static constexpr bool INTERIOR_LOOP = BK == 32;
     static constexpr int WM = WM_, WN = WN_;          // waves along m and n
     static constexpr int THREADS = 64 * WM * WN;
     static constexpr int TM = BM / WM, TN = BN / WN;  // wave tile
@@ -190,7 +196,7 @@ __device__ __forceinline__ void f32_tile(const TileProblem &P, int tm, int tn, i
     // Interior tiles (the whole tile and every k-tile inside the matrices)
     // run a loop whose loads carry no masks; edge tiles the masked one.  Both
     // do the same arithmetic in the same order.
-    const bool interior = m0 + Cfg::BM <= P.m && n0 + Cfg::BN <= P.n && kt1 * Cfg::BK <= P.k;
+    const bool interior = Cfg::INTERIOR_LOOP && m0 + Cfg::BM <= P.m && n0 + Cfg::BN <= P.n && kt1 * Cfg::BK <= P.k;
     if (interior) {
         for (int kt = kt0; kt < kt1; ++kt) {
             const int cur = (kt - kt0) & 1;
@@ -218,8 +224,8 @@ __device__ __forceinline__ void f32_tile(const TileProblem &P, int tm, int tn, i
     tile_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
 }
 
-template <int BM, int BN, int WM, int WN>
-__device__ __forceinline__ void F32Cfg<BM, BN, WM, WN>::run(const TileProblem &P, int tm, int tn, int split,
+template <int BM, int BN, int WM, int WN, int BK>
+__device__ __forceinline__ void F32Cfg<BM, BN, WM, WN, BK>::run(const TileProblem &P, int tm, int tn, int split,
                                                             uint8_t *lds) {
-    f32_tile<F32Cfg<BM, BN, WM, WN>>(P, tm, tn, split, reinterpret_cast<float *>(lds));
+    f32_tile<F32Cfg<BM, BN, WM, WN, BK>>(P, tm, tn, split, reinterpret_cast<float *>(lds));
 }
