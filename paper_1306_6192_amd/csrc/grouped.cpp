@@ -35,6 +35,31 @@ int grouped_choose(int mode, int64_t m, int64_t n, int64_t k) {
     return pick;
 }
 
+// The same choice for a problem launched on its own (a serving batch of one):
+// the two tiles give the same bits, so the one that finishes first is taken,
+// counting rounds of resident workgroups -- a mid-size product on the large
+// tile would leave most CUs idle.
+int grouped_choose_alone(int mode, int64_t m, int64_t n, int64_t k) {
+    (void)k;
+    const GroupedKernel *gk = grouped_kernel(mode);
+    int count = 0;
+    const KernelCfg *t = configs(mode, &count);
+    double best = 1e300;
+    int pick = 0;
+    for (int c = 0; c < 2; ++c) {
+        const KernelCfg &kc = t[gk->cfg_idx[c]];
+        const double tiles = (double)((m + kc.bm - 1) / kc.bm) * (double)((n + kc.bn - 1) / kc.bn);
+        const double slots = (double)num_cus() * std::max(1, kc.wg_per_cu);
+        const double eff = (kc.bm * kc.bn >= 16384) ? 1.0 : 0.6;
+        const double cost = std::ceil(tiles / slots) * kc.bm * kc.bn / eff;
+        if (cost < best * 0.999) {
+            best = cost;
+            pick = c;
+        }
+    }
+    return pick;
+}
+
 const GroupedKernel *grouped_kernel(int mode) {
     if (mode == GEMM_MODE_F32) return f32_grouped();
     return lp_grouped(mode);

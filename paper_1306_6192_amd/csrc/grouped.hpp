@@ -16,6 +16,7 @@ struct GroupPlan {
 
 const GroupedKernel *grouped_kernel(int mode);
 int grouped_choose(int mode, int64_t m, int64_t n, int64_t k);
+int grouped_choose_alone(int mode, int64_t m, int64_t n, int64_t k);
 
 // Validate the problems (one mode), choose each problem's tile configuration
 // and lay the tiles out; empty outputs are dropped.

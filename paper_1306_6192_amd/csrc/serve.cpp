@@ -204,13 +204,14 @@ int Server::launch_batch(Slot &s, std::vector<Request *> &b) {
         return GEMM_OK;
     }
     if (b.size() == 1) {
-        // A batch of one runs as a plain launch of the tile configuration the
-        // grouped kernel would give it (same tiles, no split: the same bits),
-        // without the descriptor upload.
+        // A batch of one runs as a plain launch of one of the grouped kernel's
+        // tile configurations (no split: the same bits as in a batch),
+        // without the descriptor upload; alone, the tile that spreads the
+        // product over the most CUs may finish first.
         const gemm_problem_t &p = b[0]->p;
         const GroupedKernel *gk = grouped_kernel(p.mode);
         if (!gk) return fail(GEMM_EUNSUPPORTED, "mode %d has no grouped kernel", p.mode);
-        const int cfg = gk->cfg_idx[grouped_choose(p.mode, p.m, p.n, p.k)];
+        const int cfg = gk->cfg_idx[grouped_choose_alone(p.mode, p.m, p.n, p.k)];
         int rc = enqueue_plain(p, cfg, 1, nullptr, s.stream);
         if (rc != GEMM_OK) return rc;
         MG_HIP(hipEventRecord(s.done, s.stream));
