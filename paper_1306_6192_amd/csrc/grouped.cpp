@@ -89,6 +89,22 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan) {
         double cost;
         int tiles;
     };
+    // A launch whose chosen tiles would not fill every resident-workgroup
+    // slot runs every problem on the smaller tile instead (the tile does not
+    // change the bits): a handful of mid-size problems then spread over the
+    // chip rather than over a fraction of it.
+    const int small = t[plan.gk->cfg_idx[1]].bm * t[plan.gk->cfg_idx[1]].bn <
+                              t[plan.gk->cfg_idx[0]].bm * t[plan.gk->cfg_idx[0]].bn
+                          ? 1
+                          : 0;
+    int64_t chosen_tiles = 0;
+    for (int i = 0; i < count; ++i) {
+        const gemm_problem_t &p = ps[i];
+        if (p.m == 0 || p.n == 0) continue;
+        const KernelCfg &kc = t[plan.gk->cfg_idx[grouped_choose(p.mode, p.m, p.n, p.k)]];
+        chosen_tiles += ((p.m + kc.bm - 1) / kc.bm) * ((p.n + kc.bn - 1) / kc.bn);
+    }
+    const bool underfilled = chosen_tiles < (int64_t)num_cus() * plan.gk->wg_per_cu;
     std::vector<Item> items;
     items.reserve(count);
     for (int i = 0; i < count; ++i) {
@@ -96,7 +112,7 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan) {
         if (p.m == 0 || p.n == 0) continue;
         Item it;
         memset(&it.d, 0, sizeof(it.d));
-        it.d.cfg = grouped_choose(p.mode, p.m, p.n, p.k);
+        it.d.cfg = underfilled ? small : grouped_choose(p.mode, p.m, p.n, p.k);
         const KernelCfg &kc = t[plan.gk->cfg_idx[it.d.cfg]];
         it.d.P = make_launch(p, kc, 1).P;
         it.tiles = it.d.P.tiles_m * it.d.P.tiles_n;
