@@ -16,6 +16,8 @@ static const KernelCfg kTable[] = {
     make_cfg<Lp2Cfg<GEMM_MODE_BF16, 128, 256, 4>, 1, 8>(), make_cfg<Lp2Cfg<GEMM_MODE_BF16, 128, 128, 4>, 2, 8>(),
     // eight waves (two per SIMD): 2 x 4 (128 x 64 each) and 4 x 2 (64 x 128 each)
     make_cfg<Lp2Cfg<GEMM_MODE_BF16, 256, 256, 4, 2, 4>, 2, 8>(), make_cfg<Lp2Cfg<GEMM_MODE_BF16, 256, 256, 4, 4, 2>, 2, 8>(),
+    // register-staged k-tiles of 32 (half the LDS): three workgroups per CU
+    make_cfg<LpCfg<GEMM_MODE_BF16, 128, 128, 32>, 3>(),
 };
 
 const KernelCfg *lp_configs_bf16(int *count) {
@@ -24,6 +26,6 @@ const KernelCfg *lp_configs_bf16(int *count) {
 }
 
 static const GroupedKernel kGrouped = {
-    {3, 6}, 2, launch_grouped_t<LpCfg<GEMM_MODE_BF16, 128, 128>, LpCfg<GEMM_MODE_BF16, 64, 64>, 2>};
+    {13, 6}, 3, launch_grouped_t<LpCfg<GEMM_MODE_BF16, 128, 128, 32>, LpCfg<GEMM_MODE_BF16, 64, 64>, 3>};
 
 const GroupedKernel *lp_grouped_bf16() { return &kGrouped; }

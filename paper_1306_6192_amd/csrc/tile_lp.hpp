@@ -43,16 +43,20 @@ template <> struct LpTraits<GEMM_MODE_F32_SPLIT_BF16X3> {
     static constexpr int IN_ESZ = 4, BK = 32, PLANES = 2, ROW = 64, KCH = 16, VB = 16;
 };
 
-template <int MODE_, int BM_, int BN_>
+// BK_ may halve the mode's k-tile (half the LDS, for more resident
+// workgroups); the MFMA k-steps and their order are the same.
+template <int MODE_, int BM_, int BN_, int BK_ = LpTraits<MODE_>::BK>
 struct LpCfg {
     typedef LpTraits<MODE_> T;
     static constexpr int MODE = MODE_;
-    static constexpr int BM = BM_, BN = BN_, BK = T::BK;
+    static constexpr int BM = BM_, BN = BN_, BK = BK_;
+    static constexpr int ROW = T::ROW / (T::BK / BK);   // bytes of a staged LDS row per plane
+    static_assert(BK == T::BK || 2 * BK == T::BK, "the mode's k-tile or half of it");
     static constexpr int WM = 2, WN = 2;
     static constexpr int THREADS = GEMM_THREADS;
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int RB = TM / 32, CB = TN / 32;
-    static constexpr int RS = T::ROW + 16;       // padded LDS row stride in bytes (odd multiple of 16)
+    static constexpr int RS = ROW + 16;          // padded LDS row stride in bytes (odd multiple of 16)
     static constexpr int PLANE_A = BM * RS, PLANE_B = BN * RS;
     static constexpr int A_BYTES = T::PLANES * PLANE_A, B_BYTES = T::PLANES * PLANE_B;
     static constexpr int STAGE = A_BYTES + B_BYTES;
@@ -222,7 +226,7 @@ __device__ __forceinline__ void lp_compute_stage(const uint8_t *stage, f32x16 (&
     const uint8_t *Bs = stage + Cfg::A_BYTES + (wn * Cfg::TN + l32) * Cfg::RS + g * Cfg::T::VB;
     constexpr int CHUNK_BYTES = 2 * Cfg::T::VB;   // bytes of one MFMA k-step in a row
 #pragma unroll
-    for (int kc = 0; kc < Cfg::T::ROW / CHUNK_BYTES; ++kc) {
+    for (int kc = 0; kc < Cfg::ROW / CHUNK_BYTES; ++kc) {
         if constexpr (MODE == GEMM_MODE_F8E4M3) {
             i32x8 af[Cfg::RB], bf[Cfg::CB];
 #pragma unroll
@@ -337,8 +341,8 @@ __device__ __forceinline__ void lp_tile(const TileProblem &P, int tm, int tn, in
     tile_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
 }
 
-template <int MODE, int BM, int BN>
-__device__ __forceinline__ void LpCfg<MODE, BM, BN>::run(const TileProblem &P, int tm, int tn, int split,
+template <int MODE, int BM, int BN, int BK>
+__device__ __forceinline__ void LpCfg<MODE, BM, BN, BK>::run(const TileProblem &P, int tm, int tn, int split,
                                                          uint8_t *lds) {
-    lp_tile<LpCfg<MODE, BM, BN>>(P, tm, tn, split, lds);
+    lp_tile<LpCfg<MODE, BM, BN, BK>>(P, tm, tn, split, lds);
 }
