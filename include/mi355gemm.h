@@ -108,7 +108,12 @@ typedef struct gemm_problem {
 int gemm_plain(const gemm_problem_t *p, void *stream);
 
 /* As gemm_plain with an explicit tile configuration (index into
- * gemm_config_info) and split-K factor (>= 1).  For tuning and tests. */
+ * gemm_config_info) and split-K factor (>= 1).  For tuning and tests.
+ * Configurations whose k-tile is copied straight into LDS in 16-byte chunks
+ * need k and n multiples of the chunk (16 bytes of elements), lda and ldb
+ * likewise and 16-byte aligned A and B; for any other problem the
+ * register-staged configuration of the same tile size runs instead.  Without
+ * split-K every configuration of a mode gives the same bits. */
 int gemm_plain_cfg(const gemm_problem_t *p, int32_t cfg, int32_t split_k, void *stream);
 
 /* The paper's own GPU kernels on gfx950, float32 only, as a baseline for the
@@ -140,7 +145,8 @@ int gemm_config_info(int32_t mode, int32_t cfg, int32_t info[6]);
 int gemm_plain_f64(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *B, int64_t ldb,
                    double *C, int64_t ldc, void *stream);
 /* As gemm_plain_f64 with an explicit configuration (gemm_config_info of
- * GEMM_MODE_F64).  For tests. */
+ * GEMM_MODE_F64; chunked configurations fall back as for gemm_plain_cfg, and
+ * every configuration gives the same bits).  For tests. */
 int gemm_plain_f64_cfg(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *B,
                        int64_t ldb, double *C, int64_t ldc, int32_t cfg, void *stream);
 
