@@ -618,7 +618,9 @@ def section_vendor(args, torch, mg, synth, stream, line):
     inputs, timed the same way, with its sampled error against float64 dot
     products (which shows that its FP32 path computes in FP32).  Where this
     line also holds our figure for the same product, the ratio ours/vendor is
-    given.  The vendor's 16-bit products return 16-bit C (ours float32)."""
+    given (the vendor's median of five launches after two warm-ups against
+    our mean over the section's timed launches, which does not favour us).
+    The vendor's 16-bit products return 16-bit C (ours float32)."""
     torch.backends.cuda.matmul.allow_tf32 = False
     T = Timer(torch, stream)
     ours = {(p["m"], p["n"], p["k"]): p["tflops"] for p in line.get("per_shape", [])}
