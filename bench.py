@@ -226,7 +226,7 @@ def section_plain(args, torch, mg, synth, stream, line):
                           "rel_err_sampled": relerr(C[rows, cols], R)})
         if (m, n, k) == DOMINANT:
             info = mg.config_info(mg.MODE_F32, cfg)
-            kind = "asynchronous-copy" if info["BK"] == 16 else "register-staged"
+            kind = "asynchronous-copy" if mg.config_chunk(mg.MODE_F32, cfg) > 0 else "register-staged"
             dom = (avg, tf, f"gemm_plain_kernel, FP32 {info['BM']}x{info['BN']}x{info['BK']} {kind} tile, "
                             f"{info['waves']} waves (config {cfg}), 8192^3")
     line.update({

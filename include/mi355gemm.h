@@ -130,6 +130,13 @@ int gemm_ablation(const gemm_problem_t *p, int32_t variant, void *stream);
 int gemm_num_configs(int32_t mode);
 int gemm_config_info(int32_t mode, int32_t cfg, int32_t info[6]);
 
+/* The chunk a configuration copies straight into LDS, in elements (16 bytes
+ * of the mode's element type), or 0 for a register-staged configuration that
+ * takes any shape; GEMM_EINVAL for an unknown mode or configuration.  A
+ * chunked configuration runs only where k, n, lda and ldb are multiples of
+ * the chunk and A, B are 16-byte aligned (else see gemm_plain_cfg). */
+int gemm_config_chunk(int32_t mode, int32_t cfg);
+
 /* ---------------------------------------------------------------------- */
 /* Double and complex-float products, matrix addition (the paper times the */
 /* product for float, double and complex float matrices, Results section,  */

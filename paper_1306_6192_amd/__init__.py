@@ -214,6 +214,12 @@ def config_info(mode, cfg) -> dict:
     return dict(zip(("BM", "BN", "BK", "waves", "lds_bytes", "mfma_k"), list(info)))
 
 
+def config_chunk(mode, cfg) -> int:
+    """Elements per 16-byte chunk a configuration copies straight into LDS,
+    or 0 for a register-staged configuration (gemm_config_chunk)."""
+    return check(load().gemm_config_chunk(mode, cfg))
+
+
 def tuner_lookup(mode, m, n, k):
     c = ctypes.c_int32()
     s = ctypes.c_int32()

@@ -89,6 +89,7 @@ _SIGS = {
                            c_int64, c_void_p]),
     "gemm_num_configs": (c_int32, [c_int32]),
     "gemm_config_info": (c_int32, [c_int32, c_int32, POINTER(c_int32)]),
+    "gemm_config_chunk": (c_int32, [c_int32, c_int32]),
     "gemm_convert_f32": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "gemm_quantize_e4m3": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "gemm_errnorm": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p]),

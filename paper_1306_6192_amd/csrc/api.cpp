@@ -316,6 +316,15 @@ int gemm_config_info(int32_t mode, int32_t cfg, int32_t info[6]) {
     return GEMM_OK;
 }
 
+int gemm_config_chunk(int32_t mode, int32_t cfg) {
+    clear_error();
+    if (mode < 0 || mode >= GEMM_NUM_KERNEL_FAMILIES) return fail(GEMM_EINVAL, "unknown mode %d", mode);
+    int count = 0;
+    const KernelCfg *t = configs(mode, &count);
+    if (cfg < 0 || cfg >= count) return fail(GEMM_EINVAL, "config %d out of range", cfg);
+    return t[cfg].chunk;
+}
+
 static int plain_common(const gemm_problem_t *p, int cfg, int split, void *stream) {
     int rc = validate(p);
     if (rc != GEMM_OK) return rc;

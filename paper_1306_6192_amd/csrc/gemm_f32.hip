@@ -35,6 +35,13 @@ static const KernelCfg kF32Configs[] = {
     // register-staged k-tiles of 16 (half the LDS): three workgroups per CU
     make_cfg<F32Cfg<128, 128, 2, 2, 16>, 3>(),
     make_cfg<F32Cfg<64, 64, 2, 2, 16>, 3>(),
+    // asynchronous-copy tiles with k-tiles of 32 (128-byte A rows) in two
+    // LDS stages: half the barriers of the k-tile-16 ring, and the loads of
+    // the next k-tile still have a whole k-tile of MFMAs to land
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 256, 2, 2, 2, 128>, 1, 4>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 128, 2, 2, 2, 128>, 1, 4>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 128, 256, 2, 2, 2, 128>, 1, 4>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F32, 128, 128, 2, 2, 2, 128>, 2, 4>(),
 };
 
 const KernelCfg *f32_configs(int *count) {

@@ -69,7 +69,8 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <int MODE_, int BM_, int BN_, int STAGES_, int WM_ = 2, int WN_ = 2>
+// AROWB_: bytes of an A row per k-tile (0: the mode's own, 64 or 128).
+template <int MODE_, int BM_, int BN_, int STAGES_, int WM_ = 2, int WN_ = 2, int AROWB_ = 0>
 struct Lp2Cfg {
     static constexpr int MODE = MODE_;
     static constexpr int BM = BM_, BN = BN_, STAGES = STAGES_;
@@ -85,7 +86,7 @@ struct Lp2Cfg {
     static constexpr int CBA = C32 ? 2 * CB : CB;       // accumulator blocks per row block
     static constexpr int ESZ = (MODE == GEMM_MODE_F8E4M3) ? 1 : (F64 || C32) ? 8 : F32 ? 4 : 2;
     static constexpr int CE = 16 / ESZ;                 // elements per 16-byte chunk
-    static constexpr int A_ROWB = (F64 || C32) ? 128 : 64;   // bytes of an A row per k-tile
+    static constexpr int A_ROWB = AROWB_ ? AROWB_ : (F64 || C32) ? 128 : 64;   // bytes of an A row per k-tile
     static constexpr int A_CPR = A_ROWB / 16;           // 16-byte chunks per A row
     static constexpr int BK = A_ROWB / ESZ;             // k per k-tile
     // k per step: one MFMA (16- and 8-bit), four 32x32x2 MFMAs (FP32), four
@@ -509,16 +510,21 @@ __device__ __forceinline__ void lp2_step(const Lp2Src<Cfg> &S, int kt0, int i, i
 }
 
 // All steps of k-tile i (stage u).  On entry `fa` holds the tile's step-0
-// fragments; on exit the next tile's step-0 fragments are in `fa` (two steps
-// per k-tile) or in `fb` (one step).
+// fragments; on exit the next tile's step-0 fragments are in `fa` (an even
+// number of steps per k-tile) or in `fb` (one step).
 template <class Cfg, bool CHECK>
 __device__ __forceinline__ void lp2_ktile(const Lp2Src<Cfg> &S, int kt0, int i, int u, uint8_t *lds,
                                           Lp2Frag<Cfg> &fa, Lp2Frag<Cfg> &fb, typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CBA]) {
-    if constexpr (Cfg::STEPS == 2) {
-        lp2_step<Cfg, false, CHECK>(S, kt0, i, u, 0, lds, fa, fb, acc);
-        lp2_step<Cfg, true, CHECK>(S, kt0, i, u, 1, lds, fb, fa, acc);
-    } else {
+    if constexpr (Cfg::STEPS == 1) {
         lp2_step<Cfg, true, CHECK>(S, kt0, i, u, 0, lds, fa, fb, acc);
+    } else {
+#pragma unroll
+        for (int kc = 0; kc + 2 < Cfg::STEPS; kc += 2) {
+            lp2_step<Cfg, false, CHECK>(S, kt0, i, u, kc, lds, fa, fb, acc);
+            lp2_step<Cfg, false, CHECK>(S, kt0, i, u, kc + 1, lds, fb, fa, acc);
+        }
+        lp2_step<Cfg, false, CHECK>(S, kt0, i, u, Cfg::STEPS - 2, lds, fa, fb, acc);
+        lp2_step<Cfg, true, CHECK>(S, kt0, i, u, Cfg::STEPS - 1, lds, fb, fa, acc);
     }
 }
 
@@ -530,14 +536,14 @@ __device__ __forceinline__ void lp2_pair(const Lp2Src<Cfg> &S, int kt0, int i, i
                                          typename Cfg::Acc (&acc)[Cfg::RB][Cfg::CBA]) {
     if (!guard || i < nt) lp2_ktile<Cfg, CHECK>(S, kt0, i, u, lds, f0, f1, acc);
     if (!guard || i + 1 < nt) {
-        if constexpr (Cfg::STEPS == 2) lp2_ktile<Cfg, CHECK>(S, kt0, i + 1, u + 1, lds, f0, f1, acc);
+        if constexpr (Cfg::STEPS % 2 == 0) lp2_ktile<Cfg, CHECK>(S, kt0, i + 1, u + 1, lds, f0, f1, acc);
         else lp2_ktile<Cfg, CHECK>(S, kt0, i + 1, u + 1, lds, f1, f0, acc);
     }
 }
 
 template <class Cfg>
 __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, int split, uint8_t *lds) {
-    static_assert(Cfg::STEPS == 1 || Cfg::STEPS == 2, "pipeline written for 1 or 2 steps per k-tile");
+    static_assert(Cfg::STEPS == 1 || Cfg::STEPS % 2 == 0, "pipeline written for 1 or an even number of steps per k-tile");
     static_assert(Cfg::STAGES % 2 == 0, "k-tiles are processed in pairs of stages");
     const int m0 = tm * Cfg::BM, n0 = tn * Cfg::BN;
     const int nkt = (P.k + Cfg::BK - 1) / Cfg::BK;
@@ -606,8 +612,8 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
     }
 }
 
-template <int MODE, int BM, int BN, int STAGES, int WM, int WN>
-__device__ __forceinline__ void Lp2Cfg<MODE, BM, BN, STAGES, WM, WN>::run(const TileProblem &P, int tm, int tn,
+template <int MODE, int BM, int BN, int STAGES, int WM, int WN, int AROWB>
+__device__ __forceinline__ void Lp2Cfg<MODE, BM, BN, STAGES, WM, WN, AROWB>::run(const TileProblem &P, int tm, int tn,
                                                                            int split, uint8_t *lds) {
-    lp2_tile<Lp2Cfg<MODE, BM, BN, STAGES, WM, WN>>(P, tm, tn, split, lds);
+    lp2_tile<Lp2Cfg<MODE, BM, BN, STAGES, WM, WN, AROWB>>(P, tm, tn, split, lds);
 }

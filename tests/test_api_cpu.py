@@ -116,6 +116,18 @@ def test_config_tables():
     assert lib.gemm_num_configs(9) == _lib.GEMM_EINVAL
 
 
+def test_config_chunk():
+    """Chunked (asynchronous-copy) configurations report 16 bytes of their
+    element type; register-staged ones 0; each family has both kinds."""
+    lib = _lib.load()
+    elems = {0: 4, 1: 8, 2: 8, 3: 16, _lib.MODE_F64: 2, _lib.MODE_C32: 2}
+    for mode, ce in elems.items():
+        chunks = [lib.gemm_config_chunk(mode, c) for c in range(lib.gemm_num_configs(mode))]
+        assert set(chunks) == {0, ce}, (mode, chunks)
+    assert lib.gemm_config_chunk(0, lib.gemm_num_configs(0)) == _lib.GEMM_EINVAL
+    assert lib.gemm_config_chunk(-1, 0) == _lib.GEMM_EINVAL
+
+
 def test_tuner_lookup_is_a_pure_function_of_shape(tmp_path):
     lib = _lib.load()
     c1, s1, c2, s2 = (ctypes.c_int32() for _ in range(4))

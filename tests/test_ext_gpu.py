@@ -127,7 +127,7 @@ F64_CHUNKED = [(1, 2, 2), (33, 34, 18), (64, 512, 16), (129, 66, 18), (257, 130,
 
 
 def _f64_async_configs():
-    return [c for c in range(mg.num_configs(mg.MODE_F64)) if mg.config_info(mg.MODE_F64, c)["lds_bytes"] >= 131072]
+    return [c for c in range(mg.num_configs(mg.MODE_F64)) if mg.config_chunk(mg.MODE_F64, c) > 0]
 
 
 @pytest.mark.parametrize("m,n,k", F64_CHUNKED)
@@ -268,7 +268,7 @@ C32_CHUNKED = [(1, 2, 2), (33, 34, 18), (64, 256, 16), (129, 66, 26), (257, 130,
 
 
 def _c32_async_configs():
-    return [c for c in range(mg.num_configs(mg.MODE_C32)) if mg.config_info(mg.MODE_C32, c)["lds_bytes"] >= 131072]
+    return [c for c in range(mg.num_configs(mg.MODE_C32)) if mg.config_chunk(mg.MODE_C32, c) > 0]
 
 
 @pytest.mark.parametrize("m,n,k", C32_CHUNKED)

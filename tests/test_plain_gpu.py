@@ -143,7 +143,7 @@ CHUNKED_SHAPES = [(1, 4, 4), (33, 36, 20), (64, 512, 16), (129, 388, 8), (257, 1
 
 
 def _chunked_configs():
-    return [c for c in _configs() if mg.config_info(mg.MODE_F32, c)["BK"] == 16]
+    return [c for c in _configs() if mg.config_chunk(mg.MODE_F32, c) > 0]
 
 
 @pytest.mark.parametrize("m,n,k", CHUNKED_SHAPES)
