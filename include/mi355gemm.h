@@ -112,8 +112,11 @@ int gemm_plain(const gemm_problem_t *p, void *stream);
  * Configurations whose k-tile is copied straight into LDS in 16-byte chunks
  * need k and n multiples of the chunk (16 bytes of elements), lda and ldb
  * likewise and 16-byte aligned A and B; for any other problem the
- * register-staged configuration of the same tile size runs instead.  Without
- * split-K every configuration of a mode gives the same bits. */
+ * register-staged configuration of the same tile size runs instead.  Split-K
+ * cuts k into ranges of whole grains (32 k for FP32 and split-BF16x3, 64 for
+ * BF16 and F16, 128 for FP8), each a whole number of every configuration's
+ * k-tiles, so for a given split factor every configuration of a mode gives
+ * the same bits. */
 int gemm_plain_cfg(const gemm_problem_t *p, int32_t cfg, int32_t split_k, void *stream);
 
 /* The paper's own GPU kernels on gfx950, float32 only, as a baseline for the
@@ -217,7 +220,13 @@ int gemm_graph_destroy(void *graph);
 /* Tuning table (project autotuner).                                       */
 
 /* Time every legal configuration and split-K factor for this shape on the
- * current device and record the fastest in the table (synchronises). */
+ * current device and record the fastest in the table (synchronises).  The
+ * library allocates the operands and fills them with non-zero pseudo-random
+ * values of the mode's type (the clock under load depends on the data); each
+ * choice is the median of five launches, and the choices within 3 % of the
+ * fastest are timed three more times in turn before the fastest is kept.
+ * Errors: GEMM_EINVAL (unknown mode, an empty product), GEMM_ENOMEM (the
+ * operands do not fit), GEMM_EHIP. */
 int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
 /* The (cfg, split_k) gemm_plain would use for this shape. */
 int gemm_tuner_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t *cfg, int32_t *split_k);

@@ -18,6 +18,11 @@ static const KernelCfg kTable[] = {
     make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 4, 2, 4>, 2, 8>(), make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 4, 4, 2>, 2, 8>(),
     // register-staged k-tiles of 32 (half the LDS): three workgroups per CU
     make_cfg<LpCfg<GEMM_MODE_F16, 128, 128, 32>, 3>(),
+    // asynchronous-copy k-tiles of 64 (128-byte A rows) in two LDS stages:
+    // half the barriers of the k-tile-32 ring, eight waves (2 x 4, 4 x 2) or four
+    make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 2, 2, 4, 128>, 2, 8>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 2, 4, 2, 128>, 2, 8>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 2, 2, 2, 128>, 1, 8>(),
 };
 
 const KernelCfg *lp_configs_f16(int *count) {

@@ -16,16 +16,18 @@ static const KernelCfg kTable[] = {
 const KernelCfg *lp_configs_bf16(int *count);
 
 // The register-staged tiles above (any shape; the grouped launch uses two of
-// them), then one pre-split entry per asynchronous-copy BF16 tile: those run
-// the split form as a BF16 product over interleaved operand copies and give
-// the same bits (the BF16 kernels themselves live in the BF16 table).
+// them), then one pre-split entry per asynchronous-copy BF16 tile with
+// k-tiles of 32: those run the split form as a BF16 product over interleaved
+// operand copies and give the same bits (the BF16 kernels themselves live in
+// the BF16 table).  A 32-k split-K grain of the split form is three such
+// k-tiles of the interleaved product; a k-tile of 64 would straddle grains.
 const KernelCfg *lp_configs_split(int *count) {
     static const std::vector<KernelCfg> table = [] {
         std::vector<KernelCfg> t(std::begin(kTable), std::end(kTable));
         int nb = 0;
         const KernelCfg *bf = lp_configs_bf16(&nb);
         for (int c = 0; c < nb; ++c)
-            if (bf[c].chunk) {
+            if (bf[c].chunk && bf[c].bk == 32) {
                 KernelCfg k = bf[c];
                 k.chunk = 0;
                 k.presplit = 1;

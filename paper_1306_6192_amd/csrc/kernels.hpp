@@ -59,6 +59,7 @@ const GroupedKernel *lp_grouped(int mode);
 
 // Elementwise / reduction kernels (misc.hip).
 hipError_t launch_fill_zero(float *C, int64_t ldc, int m, int n, hipStream_t s);
+hipError_t launch_fill_tuning(void *p, int64_t count, int elem_bytes, uint32_t seed, hipStream_t s);
 hipError_t launch_splitk_reduce(const float *ws, int64_t split_stride, int splits, float scale,
                                 float *C, int64_t ldc, int m, int n, hipStream_t s);
 hipError_t launch_convert_f32(const float *x, int64_t count, int to_mode, void *out, hipStream_t s);

@@ -42,6 +42,44 @@ __global__ void splitk_reduce_kernel(const float *__restrict__ ws, int64_t split
     }
 }
 
+// Tuning operands: element i of a buffer of `count` elements gets a value in
+// (-4, 4) from a hash of i (a 32-bit integer mix), so the timed products
+// toggle the matrix cores and draw the power that real data draws (all-zero
+// operands let the clock run higher than any real product would).  Element
+// types: 4 = float32, 2 = the upper half of the float32 value (read as
+// bfloat16 or as binary16, finite either way), 1 = E4M3 (random sign and
+// mantissa, exponent field 4..8: no NaN code).
+__device__ __forceinline__ uint32_t tune_hash(uint64_t i, uint32_t seed) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(i >> 32) * 0x85EBCA77u ^ seed;
+    h ^= h >> 16;
+    h *= 0x7FEB352Du;
+    h ^= h >> 15;
+    h *= 0x846CA68Bu;
+    h ^= h >> 16;
+    return h;
+}
+
+__global__ void fill_tuning_kernel(void *p, int64_t count, int elem_bytes, uint32_t seed) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t h = tune_hash((uint64_t)i, seed);
+        if (elem_bytes == 1) {
+            static_cast<uint8_t *>(p)[i] = (uint8_t)((h & 0x80u) | ((4u + (h >> 8) % 5u) << 3) | ((h >> 16) & 7u));
+        } else {
+            const float v = ((float)(h >> 8) * (1.f / 8388608.f) - 1.f) * 4.f;
+            if (elem_bytes == 4) static_cast<float *>(p)[i] = v;
+            else static_cast<uint16_t *>(p)[i] = (uint16_t)(__float_as_uint(v) >> 16);
+        }
+    }
+}
+
+hipError_t launch_fill_tuning(void *p, int64_t count, int elem_bytes, uint32_t seed, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_tuning_kernel, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, count, elem_bytes,
+                       seed);
+    return hipGetLastError();
+}
+
 hipError_t launch_splitk_reduce(const float *ws, int64_t split_stride, int splits, float scale,
                                 float *C, int64_t ldc, int m, int n, hipStream_t s) {
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for((int64_t)m * n, 256, 8192)), dim3(256), 0, s,

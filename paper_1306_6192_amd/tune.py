@@ -4,8 +4,9 @@ the current GPU and write the tuning table the library loads at start-up.
     python -m paper_1306_6192_amd.tune [--out PATH]
 
 Every entry is chosen by `gemm_tune` (the library times each legal
-configuration and split-K factor with HIP events and keeps the fastest); the
-table is keyed by (mode, m, n, k) only.
+configuration and split-K factor with HIP events on non-zero operands,
+re-times the near-ties and keeps the fastest); the table is keyed by
+(mode, m, n, k) only.
 """
 from __future__ import annotations
 

@@ -116,6 +116,18 @@ def test_config_tables():
     assert lib.gemm_num_configs(9) == _lib.GEMM_EINVAL
 
 
+def test_k_tiles_divide_the_split_grain():
+    """Split-K hands each split whole grains of k (32 for FP32 and
+    split-BF16x3, 64 for BF16/F16, 128 for FP8); a k-tile that does not divide
+    the grain would straddle two splits."""
+    lib = _lib.load()
+    info = (ctypes.c_int32 * 6)()
+    for mode, grain in {0: 32, 1: 64, 2: 64, 3: 128, 4: 32}.items():
+        for c in range(lib.gemm_num_configs(mode)):
+            assert lib.gemm_config_info(mode, c, info) == 0
+            assert grain % info[2] == 0, (mode, c, info[2])
+
+
 def test_config_chunk():
     """Chunked (asynchronous-copy) configurations report 16 bytes of their
     element type; register-staged ones 0; each family has both kinds."""

@@ -64,3 +64,23 @@ def test_errnorm_matches_oracle_terms(m, n):
     assert out[1] == pytest.approx(sr, rel=1e-12)
     assert out[2] == mx
     assert np.sqrt(out[0] / out[1]) == pytest.approx(oracle.relerr(C, R), rel=1e-12)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 3])
+def test_tune_records_a_legal_choice(mode):
+    """gemm_tune times every legal choice on its own non-zero operands and
+    records one: the lookup returns it, it is a valid configuration and split,
+    and gemm_plain then computes the shape with it (integer inputs: exact)."""
+    m, n, k = 300, 208, 1040
+    log(f"tune mode {mode} {(m, n, k)}")
+    cfg, split = mg.tune(mode, m, n, k)
+    assert 0 <= cfg < mg.num_configs(mode) and split >= 1
+    assert mg.tuner_lookup(mode, m, n, k) == (cfg, split)
+    A, B = synth.pair(m, n, k, seed=61, dist="integers", R=4)
+    dA, dB = dev(A), dev(B)
+    if mode in (1, 2):
+        dA, dB = mg.convert(dA, mode), mg.convert(dB, mode)
+    elif mode == 3:   # integers of magnitude <= 4 are exact E4M3 values
+        dA, dB = dA.to(torch.float8_e4m3fn), dB.to(torch.float8_e4m3fn)
+    C = host(mg.gemm(dA, dB, mode=mode))
+    assert np.array_equal(C.astype(np.float64), oracle.gemm(A, B))
