@@ -55,7 +55,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--sections", default="plain,precision,grouped,serving,ablation,table2,addition,vendor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
@@ -149,16 +149,32 @@ def cpu_baseline(A, B, target_s: float):
             "sample": f"{total_rows} full rows of the {m}x{n}x{k} product (binary64 loop), {total_t:.1f} s"}
 
 
+# Device time each secondary measurement runs before its timed calls.
+WARM_MS = 100.0
+
+
 class Timer:
     """HIP-event timing of work enqueued on one stream."""
 
     def __init__(self, torch, stream):
         self.torch, self.stream = torch, stream
 
-    def time(self, fn, reps, warmup=1):
+    def time(self, fn, reps, warmup=1, warm_ms=0.0):
+        """Per-call milliseconds of `reps` calls, after `warmup` calls and
+        then, if `warm_ms` > 0, as many more as fill about warm_ms of device
+        time (the clock of an idle GPU takes tens of milliseconds of load to
+        settle)."""
         torch = self.torch
         for _ in range(warmup):
             fn()
+        if warm_ms > 0:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(self.stream)
+            fn()
+            e1.record(self.stream)
+            torch.cuda.synchronize()
+            for _ in range(min(1000, int(warm_ms / max(e0.elapsed_time(e1), 1e-3)))):
+                fn()
         torch.cuda.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for e0, e1 in evs:
@@ -292,7 +308,8 @@ def section_precision(args, torch, mg, synth, stream, line):
                 a, b, sa, sb = dA, dB, 1.0, 1.0
             # warm-up launches first: the clock settles at its sustained level
             # under matrix-core load only after a few milliseconds
-            ms = T.time(lambda: mg.gemm(a, b, out=C, mode=mode, scale_a=sa, scale_b=sb, stream=stream), 10, warmup=3)
+            ms = T.time(lambda: mg.gemm(a, b, out=C, mode=mode, scale_a=sa, scale_b=sb, stream=stream), 10, warmup=3,
+                        warm_ms=WARM_MS)
             avg = float(np.mean(ms))
             tf = 2.0 * m * n * k / (avg / 1e3) / 1e12
             got = C.cpu().numpy()[rows, cols]
@@ -519,7 +536,7 @@ def section_ablation(args, torch, mg, synth, stream, line):
     for name, fn in (("paper_global_memory", lambda: mg.paper_kernel(dA, dB, out=C, variant=0, stream=stream)),
                      ("paper_lds_16x16", lambda: mg.paper_kernel(dA, dB, out=C, variant=1, stream=stream)),
                      ("mfma_tiled", lambda: mg.gemm(dA, dB, out=C, stream=stream))):
-        ms = T.time(fn, 3, warmup=1)
+        ms = T.time(fn, 3, warmup=1, warm_ms=WARM_MS)
         avg = float(np.mean(ms))
         res.append({"kernel": name, "seconds": round(avg / 1e3, 6),
                     "tflops": round(2.0 * m * n * k / (avg / 1e3) / 1e12, 3),
@@ -544,7 +561,7 @@ def section_table2(args, torch, mg, synth, stream, line):
         A, B = synth.pair64(size, size, size, seed=0)
         dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
         C = torch.empty((size, size), dtype=torch.float64, device="cuda")
-        ms = T.time(lambda: mg.gemm_f64(dA, dB, out=C, stream=stream), 5, warmup=1)
+        ms = T.time(lambda: mg.gemm_f64(dA, dB, out=C, stream=stream), 5, warmup=1, warm_ms=WARM_MS)
         avg = float(np.mean(ms))
         R = ref_sampled(A, B, rows, cols)
         tf = 2.0 * size ** 3 / (avg / 1e3) / 1e12
@@ -556,7 +573,7 @@ def section_table2(args, torch, mg, synth, stream, line):
         A, B = synth.pair_c64(size, size, size, seed=0)
         dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
         C = torch.empty((size, size), dtype=torch.complex64, device="cuda")
-        ms = T.time(lambda: mg.gemm_c32(dA, dB, out=C, stream=stream), 5, warmup=1)
+        ms = T.time(lambda: mg.gemm_c32(dA, dB, out=C, stream=stream), 5, warmup=1, warm_ms=WARM_MS)
         avg = float(np.mean(ms))
         R = ref_sampled_complex(A, B, rows, cols)
         tf = 8.0 * size ** 3 / (avg / 1e3) / 1e12      # real flops of the complex product
@@ -647,7 +664,7 @@ def section_vendor(args, torch, mg, synth, stream, line):
         A, B = synth.pair(m, n, k, seed=0)
         dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
         C = torch.empty((m, n), device="cuda")
-        ms = T.time(lambda: torch.matmul(dA, dB, out=C), 5, warmup=2)
+        ms = T.time(lambda: torch.matmul(dA, dB, out=C), 5, warmup=2, warm_ms=WARM_MS)
         rec("fp32 torch.matmul", m, n, k, ms, C, A, B, ours_tf=ours.get((m, n, k)))
         del dA, dB, C
     m = n = k = 8192
@@ -656,26 +673,27 @@ def section_vendor(args, torch, mg, synth, stream, line):
     for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
         a, b = dA.to(dt), dB.to(dt)
         C = torch.empty((m, n), dtype=dt, device="cuda")
-        ms = T.time(lambda: torch.matmul(a, b, out=C), 5, warmup=2)
+        ms = T.time(lambda: torch.matmul(a, b, out=C), 5, warmup=2, warm_ms=WARM_MS)
         rec(f"{name} torch.matmul ({name} C)", m, n, k, ms, None, None, None, ours_tf=ours_prec.get(name))
         del a, b, C
     a8 = dA.to(torch.float8_e4m3fn)
     b8t = dB.t().contiguous().to(torch.float8_e4m3fn)
     one = torch.tensor(1.0, device="cuda")
-    ms = T.time(lambda: torch._scaled_mm(a8, b8t.t(), scale_a=one, scale_b=one, out_dtype=torch.float32), 5, warmup=2)
+    ms = T.time(lambda: torch._scaled_mm(a8, b8t.t(), scale_a=one, scale_b=one, out_dtype=torch.float32), 5, warmup=2,
+                warm_ms=WARM_MS)
     rec("e4m3 torch._scaled_mm (float32 C)", m, n, k, ms, None, None, None, ours_tf=ours_prec.get("e4m3"))
     del a8, b8t
     ours_t2 = {(r["type"], r["size"]): r.get("tflops", r.get("tflops_real"))
                for r in line.get("table2", {}).get("products", [])}
     A64, B64 = synth.pair64(m, n, k, seed=0)
     d64a, d64b = torch.from_numpy(A64).cuda(), torch.from_numpy(B64).cuda()
-    ms = T.time(lambda: torch.matmul(d64a, d64b), 3, warmup=1)
+    ms = T.time(lambda: torch.matmul(d64a, d64b), 3, warmup=1, warm_ms=WARM_MS)
     rec("f64 torch.matmul", m, n, k, ms, None, None, None, ours_tf=ours_t2.get(("double", 8192)))
     del d64a, d64b, dA, dB
     n4 = 4096
     Ac, Bc = synth.pair_c64(n4, n4, n4, seed=0)
     dca, dcb = torch.from_numpy(Ac).cuda(), torch.from_numpy(Bc).cuda()
-    ms = T.time(lambda: torch.matmul(dca, dcb), 5, warmup=2)
+    ms = T.time(lambda: torch.matmul(dca, dcb), 5, warmup=2, warm_ms=WARM_MS)
     rec("complex64 torch.matmul (real flops 8mnk)", n4, n4, n4, ms, None, None, None, flops_per_mac=8,
         ours_tf=ours_t2.get(("complex_float", 4096)))
     del dca, dcb
