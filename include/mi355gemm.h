@@ -24,7 +24,9 @@
  *    m, n, k >= 0; lda >= max(1,k); ldb >= max(1,n); ldc >= max(1,n);
  *    non-NULL pointers for non-empty operands; a known mode; FP8 scales
  *    finite and > 0; C must not overlap A or B.  Violations return
- *    GEMM_EINVAL (or GEMM_EUNSUPPORTED for a mode an entry point lacks).
+ *    GEMM_EINVAL (or GEMM_EUNSUPPORTED for a mode an entry point lacks, and
+ *    for m, n or k above 2^30).  Offsets are formed in 64 bits: C and the
+ *    operands may hold more than 2^31 elements.
  *  - k == 0 writes zeros to C (the empty sum); m == 0 or n == 0 is a no-op.
  *  - A failing HIP call returns GEMM_EHIP with the HIP error text.
  *  - Loading the library makes no HIP call; functions may be called from

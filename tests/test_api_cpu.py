@@ -247,3 +247,19 @@ def test_add_validates():
     assert lib.gemm_add(F32, 0, 4, 5, A_PTR, 5, B_PTR, 5, A_PTR + 4, 5, None) == _lib.GEMM_EINVAL
     assert lib.gemm_add(F64, 1, 4, 5, A_PTR, 5, B_PTR, 5, B_PTR, 6, None) == _lib.GEMM_EINVAL
     assert lib.gemm_add(F32, 0, 0, 5, None, 5, None, 5, None, 5, None) == _lib.GEMM_OK
+
+
+@pytest.mark.parametrize("dim", ["m", "n", "k"])
+def test_dimensions_above_2_30_are_unsupported(dim):
+    """Tile indices and per-dimension counters are 32-bit: a dimension above
+    2^30 is refused before any HIP call (offsets themselves are 64-bit)."""
+    lib = _lib.load()
+    big = (1 << 30) + 1
+    kw = {dim: big}
+    if dim == "k":
+        kw["lda"] = big
+    if dim == "n":
+        kw.update(ldb=big, ldc=big)
+    p = _prob(**kw)
+    assert lib.gemm_plain(ctypes.byref(p), None) == _lib.GEMM_EUNSUPPORTED
+    assert "2^30" in _lib.last_error()
