@@ -266,18 +266,25 @@ void DevBuf::release() {
 }
 
 struct StreamWs {
+    std::mutex mu;   // held by the caller from ensure() to the enqueue of the work that uses a slot
     DevBuf slot[4];
 };
 static std::mutex g_ws_mu;
 static std::map<std::pair<int, hipStream_t>, StreamWs *> g_ws;
 
-DevBuf *stream_workspace(hipStream_t s, int slot) {
+static StreamWs *stream_ws(hipStream_t s) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lk(g_ws_mu);
     StreamWs *&w = g_ws[{dev, s}];
     if (!w) w = new StreamWs();
-    return &w->slot[slot];
+    return w;
+}
+
+DevBuf *stream_workspace(hipStream_t s, int slot) { return &stream_ws(s)->slot[slot]; }
+
+std::unique_lock<std::mutex> lock_stream_workspaces(hipStream_t s) {
+    return std::unique_lock<std::mutex>(stream_ws(s)->mu);
 }
 
 }  // namespace mg
@@ -331,6 +338,7 @@ static int plain_common(const gemm_problem_t *p, int cfg, int split, void *strea
     hipStream_t s = (hipStream_t)stream;
     if (p->m == 0 || p->n == 0) return GEMM_OK;
     void *ws = nullptr;
+    std::unique_lock<std::mutex> ws_lock = lock_stream_workspaces(s);
     if (p->k > 0) {
         int count = 0;
         configs(p->mode, &count);
@@ -386,6 +394,7 @@ int gemm_quantize_e4m3(const float *x, int64_t count, uint8_t *q, float *scale_o
     if (count > 0 && (!x || !q)) return fail(GEMM_EINVAL, "NULL buffer");
     if (count > 0 && overlaps(x, (size_t)count * 4, q, (size_t)count)) return fail(GEMM_EINVAL, "buffers overlap");
     hipStream_t s = (hipStream_t)stream;
+    std::unique_lock<std::mutex> ws_lock = lock_stream_workspaces(s);
     DevBuf *b = stream_workspace(s, 2);
     int rc = b->ensure(4096, s);
     if (rc != GEMM_OK) return rc;
@@ -402,6 +411,7 @@ int gemm_errnorm(const float *C, int64_t ldc, const double *R, int64_t ldr, int6
     if (m * n > 0 && (!C || !R)) return fail(GEMM_EINVAL, "NULL matrix");
     hipStream_t s = (hipStream_t)stream;
     const int nparts = 2048;
+    std::unique_lock<std::mutex> ws_lock = lock_stream_workspaces(s);
     DevBuf *b = stream_workspace(s, 2);
     int rc = b->ensure(4096 + (size_t)nparts * 3 * sizeof(double), s);
     if (rc != GEMM_OK) return rc;

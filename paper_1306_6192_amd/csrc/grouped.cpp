@@ -249,6 +249,7 @@ int gemm_grouped(const gemm_problem_t *ps, int32_t count, void *stream) {
     int32_t *cnt = nullptr;
     rc = stream_counters(s, &cnt);
     if (rc != GEMM_OK) return rc;
+    std::unique_lock<std::mutex> ws_lock = lock_stream_workspaces(s);
     rc = upload_descs(plan, s, &dd);
     if (rc != GEMM_OK) return rc;
     return enqueue_group(plan, dd, cnt, s);

@@ -5,6 +5,7 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,12 @@ struct DevBuf {
 
 // Per-stream library workspace (split-K slabs, grouped descriptors).
 DevBuf *stream_workspace(hipStream_t s, int slot);
+
+// Serialises host-side use of one (device, stream)'s workspaces: a caller
+// holds it from a workspace's ensure() until the work that reads the
+// workspace is enqueued, so that a caller on another host thread using the
+// same stream cannot free and replace the buffer in between.
+std::unique_lock<std::mutex> lock_stream_workspaces(hipStream_t s);
 
 uint64_t now_ns();
 
