@@ -30,7 +30,9 @@
  *  - k == 0 writes zeros to C (the empty sum); m == 0 or n == 0 is a no-op.
  *  - A failing HIP call returns GEMM_EHIP with the HIP error text.
  *  - Loading the library makes no HIP call; functions may be called from
- *    several host threads (the tuning table is lock-protected).
+ *    several host threads (the tuning table is lock-protected, and each
+ *    (device, stream) workspace is locked from its growth to the enqueue of
+ *    the work that uses it, so threads may share a stream).
  */
 #ifndef MI355GEMM_H
 #define MI355GEMM_H
