@@ -172,3 +172,44 @@ def test_relerr_definition():
     assert oracle.relerr(np.ones((1, 1)), np.zeros((1, 1))) == 1.0
     s, r, mx = oracle.errnorm_terms(C, R)
     assert (s, r, mx) == (0.25, 25.0, 0.5)
+
+
+def test_split_bf16x3_drops_exactly_the_lo_lo_term():
+    """Operands built as hi + lo with hi = 256 k (|k| in [65, 127], exact in
+    bfloat16) and |lo| <= 63 (below half an ulp of hi, and hi + lo stays in
+    hi's binade [2^14, 2^15)): the bfloat16 split of each float32 value is
+    exactly (hi, lo), so the compensated product must be
+    the exact integer product minus sum_r lo_a lo_b -- checked in int64.
+    Dropping a cross term, or keeping lo*lo, fails."""
+    g = synth.rng(77)
+
+    def operand(shape):
+        k = g.integers(65, 128, shape) * g.choice([-1, 1], shape)
+        lo = g.integers(-63, 64, shape)
+        return (256 * k + lo).astype(np.int64), lo.astype(np.int64)
+
+    A, LA = operand((9, 14))
+    B, LB = operand((14, 11))
+    got = oracle.gemm_split_bf16x3(A.astype(np.float32), B.astype(np.float32))
+    want = A @ B - LA @ LB
+    assert np.array_equal(got, want.astype(np.float64))
+    # bfloat16-exact operands (lo = 0): the plain product
+    Ah, Bh = (A - LA).astype(np.float32), (B - LB).astype(np.float32)
+    assert np.array_equal(oracle.gemm_split_bf16x3(Ah, Bh), oracle.gemm(Ah, Bh))
+
+
+def test_fp8_product_applies_both_scales_after_the_sum():
+    """E4M3 codes from the OCP table written out by hand (0x38 = 1, 0x40 = 2,
+    0x44 = 3, 0x48 = 4, 0x30 = 0.5, sign bit 0x80), so the pin does not lean on
+    the oracle's own encoder: C = s_a s_b sum_r qa qb in binary64."""
+    val = {0x38: 1.0, 0x40: 2.0, 0x44: 3.0, 0x48: 4.0, 0x30: 0.5,
+           0xB8: -1.0, 0xC0: -2.0, 0xC4: -3.0, 0xC8: -4.0, 0xB0: -0.5, 0x00: 0.0}
+    codes = np.array(sorted(val), dtype=np.uint8)
+    g = synth.rng(78)
+    qa = g.choice(codes, (6, 10)).astype(np.uint8)
+    qb = g.choice(codes, (10, 5)).astype(np.uint8)
+    va = np.vectorize(val.get)(qa).astype(np.float64)
+    vb = np.vectorize(val.get)(qb).astype(np.float64)
+    got = oracle.gemm_fp8(qa, qb, 3.0, 0.25)
+    assert np.array_equal(got, (va @ vb) * 0.75)   # small dyadic values: every step exact
+    assert np.array_equal(oracle.dequant(qa, "e4m3"), va)
