@@ -123,6 +123,14 @@ int gemm_plain(const gemm_problem_t *p, void *stream);
  * the same bits. */
 int gemm_plain_cfg(const gemm_problem_t *p, int32_t cfg, int32_t split_k, void *stream);
 
+/* Device workspace bytes gemm_plain uses for this problem (split-K partial
+ * slabs of split*m*n float32, plus the split-BF16x3 operand copies when the
+ * pre-split path runs), rounded up to 256 bytes; 0 when the chosen
+ * configuration needs none.  Same validation as gemm_plain (no memory is
+ * touched); the configuration lookup may read the device's compute-unit
+ * count. */
+int gemm_plain_workspace_bytes(const gemm_problem_t *p, uint64_t *bytes_out);
+
 /* The paper's own GPU kernels on gfx950, float32 only, as a baseline for the
  * matrix-core path: variant 0 = one thread per c_ij reading A and B from
  * global memory (Implementation section, Listing 3); variant 1 = 16x16
@@ -206,12 +214,36 @@ int gemm_errnorm(const float *C, int64_t ldc, const double *R, int64_t ldr,
 
 /* ---------------------------------------------------------------------- */
 /* Grouped product: many independent problems in one persistent launch.   */
+/* Each problem is the product of the Implementation section; running many */
+/* of them in one launch is not in the paper: it carries the paper's block */
+/* decomposition (one thread block per output tile, Fig. 5) across         */
+/* problems, with one queue of tiles over all of them.                     */
 
-/* All problems must share one mode (F32 or BF16/F16/F8E4M3/split).  The
- * problem list is copied; device descriptors live in a library workspace
- * reused by later calls on the same stream ordering (do not run two
- * gemm_grouped calls concurrently on different streams). */
+/* All problems must share one mode (F32 or BF16/F16/F8E4M3/split); each
+ * problem's tile configuration is a function of its mode and shape only
+ * (the tuning table's grouped entries, else a cost model), so its bits do
+ * not depend on the other problems, and equal gemm_plain's with split_k = 1.
+ * The problem list is copied; the device descriptors and the work-queue
+ * counters belong to the (device, stream) pair, so calls on different
+ * streams run independently, and calls on one stream are ordered by it. */
 int gemm_grouped(const gemm_problem_t *ps, int32_t count, void *stream);
+
+/* The grouped kernel of `mode`: info[0..3] = {first tile configuration,
+ * second tile configuration (indices into gemm_config_info), resident
+ * workgroups per CU, LDS bytes per workgroup}. */
+int gemm_grouped_info(int32_t mode, int32_t info[4]);
+
+/* The tile configuration a problem of this shape gets in a grouped launch
+ * (out[0]) and as a launch of its own in the server (out[1]), and out[2] = 1
+ * when both come from measured entries of the tuning table (0: cost model).
+ * A launch whose problems would not fill every resident-workgroup slot runs
+ * all of them on the smaller tile instead (see gemm_grouped_plan). */
+int gemm_grouped_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t out[3]);
+
+/* The tile configuration each problem of this list gets in gemm_grouped
+ * (cfg_out[i], -1 for an empty output); validates like gemm_grouped and
+ * enqueues nothing. */
+int gemm_grouped_plan(const gemm_problem_t *ps, int32_t count, int32_t *cfg_out);
 
 /* Build a graph that replays the grouped launch for this problem list
  * (descriptors are uploaded once, into graph-owned device memory).  The
@@ -221,7 +253,9 @@ int gemm_graph_launch(void *graph, void *stream);
 int gemm_graph_destroy(void *graph);
 
 /* ---------------------------------------------------------------------- */
-/* Tuning table (project autotuner).                                       */
+/* Tuning table (project autotuner).  Not in the paper, whose kernels use */
+/* one fixed 16x16 block: here the tile configuration and split-K factor   */
+/* of each shape are measured on the device.                               */
 
 /* Time every legal configuration and split-K factor for this shape on the
  * current device and record the fastest in the table (synchronises).  The
@@ -232,13 +266,30 @@ int gemm_graph_destroy(void *graph);
  * Errors: GEMM_EINVAL (unknown mode, an empty product), GEMM_ENOMEM (the
  * operands do not fit), GEMM_EHIP. */
 int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
-/* The (cfg, split_k) gemm_plain would use for this shape. */
+/* As gemm_tune, but the choice is recorded for the shape's bucket
+ * (floor(log2) of m, n and k), which gemm_plain consults for any shape
+ * without an exact entry; the split factor is kept as requested, and each
+ * shape of the bucket normalises it to its own k. */
+int gemm_tune_bucket(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
+/* Measure the grouped kernel's two tiles on this shape and record, for its
+ * bucket, the faster one in a batch (a grouped launch of enough identical
+ * problems, each with its own operands, to fill every resident-workgroup
+ * slot twice; at most 256 problems and 1 GiB) and the faster one alone (a
+ * launch of one problem); medians of seven event-timed launches on non-zero
+ * operands.  Synchronises.  Dimensions up to 65536.  Errors: GEMM_EINVAL,
+ * GEMM_EUNSUPPORTED, GEMM_ENOMEM, GEMM_EHIP. */
+int gemm_tune_grouped(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
+/* The (cfg, split_k) gemm_plain would use for this shape: the exact entry,
+ * else the bucket entry, else the cost model. */
 int gemm_tuner_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t *cfg, int32_t *split_k);
 int gemm_tuner_load(const char *path);
 int gemm_tuner_save(const char *path);
 
 /* ---------------------------------------------------------------------- */
-/* Serving: continuous batching of arriving products.                      */
+/* Serving: continuous batching of arriving products.  Not in the paper   */
+/* (whose host launches one product at a time, Implementation section):    */
+/* every request is the same product, admitted by the device memory it     */
+/* holds and batched into grouped launches on several streams.             */
 
 typedef struct gemm_serve_config {
     uint64_t hbm_budget_bytes;  /* admission limit on the sum of in-flight footprints */
@@ -246,7 +297,8 @@ typedef struct gemm_serve_config {
     int32_t num_streams;        /* device streams batches are spread over */
     int32_t max_batch;          /* maximum requests in one launch */
     int32_t queue_capacity;     /* maximum queued (not yet admitted) requests */
-    int32_t executor;           /* 0 = GPU, 1 = host fake executor (tests) */
+    int32_t executor;           /* 0 = GPU grouped batches, 1 = host fake executor (tests),
+                                   2 = GPU plain launches, one per request, FIFO on one stream */
     int32_t fake_fail_every;    /* fake executor: fail every Nth batch (0 = never) */
 } gemm_serve_config_t;
 
@@ -262,7 +314,10 @@ typedef struct gemm_serve_stats {
     int32_t queued, inflight;
 } gemm_serve_stats_t;
 
-/* footprint = bytes(A) + bytes(B) + 4*m*n + split-K workspace. */
+/* Admission footprint of a request under the batched executors (0, 1):
+ * bytes(A) + bytes(B) + 4*m*n (grouped launches and a batch of one use no
+ * workspace).  The plain-launch executor (2) admits each request by that
+ * plus gemm_plain_workspace_bytes(p), the workspace of its plain launch. */
 int gemm_serve_footprint(const gemm_problem_t *p, uint64_t *bytes_out);
 int gemm_serve_create(const gemm_serve_config_t *cfg, void **server_out);
 /* Enqueue one request (copied); returns a monotonic ticket.  GEMM_ENOMEM if

@@ -76,6 +76,7 @@ _P = POINTER(GemmProblem)
 _SIGS = {
     "gemm_plain": (c_int32, [_P, c_void_p]),
     "gemm_plain_cfg": (c_int32, [_P, c_int32, c_int32, c_void_p]),
+    "gemm_plain_workspace_bytes": (c_int32, [_P, POINTER(c_uint64)]),
     "gemm_ablation": (c_int32, [_P, c_int32, c_void_p]),
     "gemm_plain_f64": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
                                  c_int64, c_void_p]),
@@ -95,9 +96,14 @@ _SIGS = {
     "gemm_errnorm": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p]),
     "gemm_grouped": (c_int32, [_P, c_int32, c_void_p]),
     "gemm_grouped_graph_create": (c_int32, [_P, c_int32, POINTER(c_void_p)]),
+    "gemm_grouped_info": (c_int32, [c_int32, POINTER(c_int32)]),
+    "gemm_grouped_lookup": (c_int32, [c_int32, c_int64, c_int64, c_int64, POINTER(c_int32)]),
+    "gemm_grouped_plan": (c_int32, [_P, c_int32, POINTER(c_int32)]),
     "gemm_graph_launch": (c_int32, [c_void_p, c_void_p]),
     "gemm_graph_destroy": (c_int32, [c_void_p]),
     "gemm_tune": (c_int32, [c_int32, c_int64, c_int64, c_int64, c_void_p]),
+    "gemm_tune_bucket": (c_int32, [c_int32, c_int64, c_int64, c_int64, c_void_p]),
+    "gemm_tune_grouped": (c_int32, [c_int32, c_int64, c_int64, c_int64, c_void_p]),
     "gemm_tuner_lookup": (c_int32, [c_int32, c_int64, c_int64, c_int64, POINTER(c_int32), POINTER(c_int32)]),
     "gemm_tuner_load": (c_int32, [c_char_p]),
     "gemm_tuner_save": (c_int32, [c_char_p]),

@@ -155,8 +155,15 @@ Launch make_launch(const gemm_problem_t &p, const KernelCfg &kc, int split) {
     return L;
 }
 
+// The pre-split path runs a BF16 product over an inner dimension of 3 k16
+// (k rounded up to 16), which the tile indexes with 32-bit integers.
+bool presplit_shape_ok(int64_t n, int64_t k) {
+    const int64_t k16 = (k + 15) / 16 * 16;
+    return n % 8 == 0 && n >= 8 && 3 * k16 <= (int64_t)INT32_MAX;
+}
+
 bool cfg_eligible(const gemm_problem_t &p, const KernelCfg &kc) {
-    if (kc.presplit) return p.n % 8 == 0 && p.n >= 8;
+    if (kc.presplit) return presplit_shape_ok(p.n, p.k);
     if (kc.chunk == 0) return true;
     const int64_t c = kc.chunk;
     return p.k % c == 0 && p.n % c == 0 && p.n >= c && p.lda % c == 0 && p.ldb % c == 0 &&
@@ -373,6 +380,19 @@ int gemm_plain_cfg(const gemm_problem_t *p, int32_t cfg, int32_t split_k, void *
     if (count == 0) return fail(GEMM_EUNSUPPORTED, "mode %d has no kernels", p->mode);
     if (cfg < 0 || cfg >= count) return fail(GEMM_EINVAL, "config %d out of range [0,%d)", cfg, count);
     return plain_common(p, cfg, split_k, stream);
+}
+
+int gemm_plain_workspace_bytes(const gemm_problem_t *p, uint64_t *bytes_out) {
+    clear_error();
+    if (!bytes_out) return fail(GEMM_EINVAL, "bytes_out is NULL");
+    *bytes_out = 0;
+    int rc = validate(p);
+    if (rc != GEMM_OK) return rc;
+    if (p->m == 0 || p->n == 0 || p->k == 0) return GEMM_OK;
+    int cfg = 0, split = 1;
+    tuner_choose(p->mode, p->m, p->n, p->k, &cfg, &split);
+    *bytes_out = (uint64_t)plain_ws_bytes(*p, cfg, split);
+    return GEMM_OK;
 }
 
 int gemm_convert_f32(const float *x, int64_t count, int32_t to_mode, void *out, void *stream) {

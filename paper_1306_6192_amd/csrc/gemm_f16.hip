@@ -30,7 +30,7 @@ const KernelCfg *lp_configs_f16(int *count) {
     return kTable;
 }
 
-static const GroupedKernel kGrouped = {
-    {13, 6}, 3, launch_grouped_t<LpCfg<GEMM_MODE_F16, 128, 128, 32>, LpCfg<GEMM_MODE_F16, 64, 64>, 3>};
+static const GroupedKernel kGrouped =
+    make_grouped<LpCfg<GEMM_MODE_F16, 128, 128, 32>, LpCfg<GEMM_MODE_F16, 64, 64>, 3>(13, 6);
 
 const GroupedKernel *lp_grouped_f16() { return &kGrouped; }

@@ -49,7 +49,7 @@ const KernelCfg *f32_configs(int *count) {
     return kF32Configs;
 }
 
-static const GroupedKernel kF32Grouped = {
-    {18, 19}, 3, launch_grouped_t<F32Cfg<128, 128, 2, 2, 16>, F32Cfg<64, 64, 2, 2, 16>, 3>};
+static const GroupedKernel kF32Grouped =
+    make_grouped<F32Cfg<128, 128, 2, 2, 16>, F32Cfg<64, 64, 2, 2, 16>, 3>(18, 19);
 
 const GroupedKernel *f32_grouped() { return &kF32Grouped; }

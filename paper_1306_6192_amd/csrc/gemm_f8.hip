@@ -21,7 +21,7 @@ const KernelCfg *lp_configs_f8(int *count) {
     return kTable;
 }
 
-static const GroupedKernel kGrouped = {
-    {3, 6}, 2, launch_grouped_t<LpCfg<GEMM_MODE_F8E4M3, 128, 128>, LpCfg<GEMM_MODE_F8E4M3, 64, 64>, 2>};
+static const GroupedKernel kGrouped =
+    make_grouped<LpCfg<GEMM_MODE_F8E4M3, 128, 128>, LpCfg<GEMM_MODE_F8E4M3, 64, 64>, 2>(3, 6);
 
 const GroupedKernel *lp_grouped_f8() { return &kGrouped; }

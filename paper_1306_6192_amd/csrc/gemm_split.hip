@@ -39,7 +39,9 @@ const KernelCfg *lp_configs_split(int *count) {
     return table.data();
 }
 
-static const GroupedKernel kGrouped = {
-    {2, 5}, 2, launch_grouped_t<LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 128, 128>, LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 64, 64>, 2>};
+// two workgroups' launch bound, but the 128 x 128 tile's two-plane ring
+// leaves room in LDS for one
+static const GroupedKernel kGrouped =
+    make_grouped<LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 128, 128>, LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 64, 64>, 2>(2, 5);
 
 const GroupedKernel *lp_grouped_split() { return &kGrouped; }

@@ -13,10 +13,10 @@
 namespace mg {
 
 // Per-problem choice between the grouped kernel's two tile configurations:
-// the cost model weighs the padded tile area against the lower sustained rate
-// of the small tile.
-int grouped_choose(int mode, int64_t m, int64_t n, int64_t k) {
-    (void)k;
+// the tuning table's measured choice for the problem's shape bucket, else a
+// cost model that weighs the padded tile area against the lower sustained
+// rate of the small tile.
+static int grouped_model(int mode, int64_t m, int64_t n, bool alone) {
     const GroupedKernel *gk = grouped_kernel(mode);
     int count = 0;
     const KernelCfg *t = configs(mode, &count);
@@ -26,7 +26,10 @@ int grouped_choose(int mode, int64_t m, int64_t n, int64_t k) {
         const KernelCfg &kc = t[gk->cfg_idx[c]];
         const double tiles = (double)((m + kc.bm - 1) / kc.bm) * (double)((n + kc.bn - 1) / kc.bn);
         const double eff = (kc.bm * kc.bn >= 16384) ? 1.0 : 0.6;
-        const double cost = tiles * kc.bm * kc.bn / eff;
+        // alone, rounds of resident workgroups count: a mid-size product on
+        // the large tile would leave most CUs idle
+        const double slots = (double)num_cus() * std::max(1, gk->wg_per_cu);
+        const double cost = (alone ? std::ceil(tiles / slots) : tiles) * kc.bm * kc.bn / eff;
         if (cost < best * 0.999) {
             best = cost;
             pick = c;
@@ -35,29 +38,18 @@ int grouped_choose(int mode, int64_t m, int64_t n, int64_t k) {
     return pick;
 }
 
+int grouped_choose(int mode, int64_t m, int64_t n, int64_t k) {
+    int in_batch = 0, alone = 0;
+    if (tuner_grouped_choice(mode, m, n, k, &in_batch, &alone)) return in_batch;
+    return grouped_model(mode, m, n, false);
+}
+
 // The same choice for a problem launched on its own (a serving batch of one):
-// the two tiles give the same bits, so the one that finishes first is taken,
-// counting rounds of resident workgroups -- a mid-size product on the large
-// tile would leave most CUs idle.
+// the two tiles give the same bits, so the one that finishes first is taken.
 int grouped_choose_alone(int mode, int64_t m, int64_t n, int64_t k) {
-    (void)k;
-    const GroupedKernel *gk = grouped_kernel(mode);
-    int count = 0;
-    const KernelCfg *t = configs(mode, &count);
-    double best = 1e300;
-    int pick = 0;
-    for (int c = 0; c < 2; ++c) {
-        const KernelCfg &kc = t[gk->cfg_idx[c]];
-        const double tiles = (double)((m + kc.bm - 1) / kc.bm) * (double)((n + kc.bn - 1) / kc.bn);
-        const double slots = (double)num_cus() * std::max(1, kc.wg_per_cu);
-        const double eff = (kc.bm * kc.bn >= 16384) ? 1.0 : 0.6;
-        const double cost = std::ceil(tiles / slots) * kc.bm * kc.bn / eff;
-        if (cost < best * 0.999) {
-            best = cost;
-            pick = c;
-        }
-    }
-    return pick;
+    int in_batch = 0, alone = 0;
+    if (tuner_grouped_choice(mode, m, n, k, &in_batch, &alone)) return alone;
+    return grouped_model(mode, m, n, true);
 }
 
 const GroupedKernel *grouped_kernel(int mode) {
@@ -65,10 +57,11 @@ const GroupedKernel *grouped_kernel(int mode) {
     return lp_grouped(mode);
 }
 
-int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan) {
+int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan, int force) {
     if (count < 0) return fail(GEMM_EINVAL, "negative problem count");
     if (count > 0 && !ps) return fail(GEMM_EINVAL, "problem array is NULL");
     plan.descs.clear();
+    plan.src.clear();
     plan.total_tiles = 0;
     plan.mode = count > 0 ? ps[0].mode : GEMM_MODE_F32;
     for (int i = 0; i < count; ++i) {
@@ -88,6 +81,7 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan) {
         GroupDesc d;
         double cost;
         int tiles;
+        int src;
     };
     // A launch whose chosen tiles would not fill every resident-workgroup
     // slot runs every problem on the smaller tile instead (the tile does not
@@ -101,10 +95,10 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan) {
     for (int i = 0; i < count; ++i) {
         const gemm_problem_t &p = ps[i];
         if (p.m == 0 || p.n == 0) continue;
-        const KernelCfg &kc = t[plan.gk->cfg_idx[grouped_choose(p.mode, p.m, p.n, p.k)]];
+        const KernelCfg &kc = t[plan.gk->cfg_idx[force >= 0 ? force : grouped_choose(p.mode, p.m, p.n, p.k)]];
         chosen_tiles += ((p.m + kc.bm - 1) / kc.bm) * ((p.n + kc.bn - 1) / kc.bn);
     }
-    const bool underfilled = chosen_tiles < (int64_t)num_cus() * plan.gk->wg_per_cu;
+    const bool underfilled = force < 0 && chosen_tiles < (int64_t)num_cus() * plan.gk->wg_per_cu;
     std::vector<Item> items;
     items.reserve(count);
     for (int i = 0; i < count; ++i) {
@@ -112,7 +106,8 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan) {
         if (p.m == 0 || p.n == 0) continue;
         Item it;
         memset(&it.d, 0, sizeof(it.d));
-        it.d.cfg = underfilled ? small : grouped_choose(p.mode, p.m, p.n, p.k);
+        it.src = i;
+        it.d.cfg = force >= 0 ? force : underfilled ? small : grouped_choose(p.mode, p.m, p.n, p.k);
         const KernelCfg &kc = t[plan.gk->cfg_idx[it.d.cfg]];
         it.d.P = make_launch(p, kc, 1).P;
         it.tiles = it.d.P.tiles_m * it.d.P.tiles_n;
@@ -128,6 +123,7 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan) {
         start += it.tiles;
         if (start > INT32_MAX) return fail(GEMM_EUNSUPPORTED, "grouped launch above 2^31 tiles");
         plan.descs.push_back(it.d);
+        plan.src.push_back(it.src);
     }
     plan.total_tiles = (int)start;
     plan.nwg = (int)std::min<int64_t>(start, (int64_t)num_cus() * plan.gk->wg_per_cu);
@@ -226,6 +222,35 @@ int upload_descs(const GroupPlan &plan, hipStream_t s, const GroupDesc **dev_out
     return GEMM_OK;
 }
 
+// Median of `reps` event-timed runs of `run` on stream `s`, after one
+// untimed run.
+template <class F>
+static int time_median(hipStream_t s, int reps, F run, float *ms_out) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MG_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GEMM_EHIP, "event creation failed");
+    }
+    std::vector<float> ts;
+    int rc = run();
+    for (int r = 0; r < reps && rc == GEMM_OK; ++r) {
+        (void)hipEventRecord(e0, s);
+        rc = run();
+        (void)hipEventRecord(e1, s);
+        if (rc == GEMM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(GEMM_EHIP, "event sync failed");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ts.push_back(ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != GEMM_OK) return rc;
+    std::sort(ts.begin(), ts.end());
+    *ms_out = ts[ts.size() / 2];
+    return GEMM_OK;
+}
+
 struct GroupGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -293,6 +318,127 @@ int gemm_grouped_graph_create(const gemm_problem_t *ps, int32_t count, void **gr
         }
     }
     *graph_out = g;
+    return GEMM_OK;
+}
+
+int gemm_tune_grouped(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream) {
+    clear_error();
+    if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
+    if (m <= 0 || n <= 0 || k <= 0) return fail(GEMM_EINVAL, "tuning needs a non-empty product");
+    if (m > 65536 || n > 65536 || k > 65536) return fail(GEMM_EUNSUPPORTED, "tuning shapes are limited to 65536");
+    const GroupedKernel *gk = grouped_kernel(mode);
+    if (!gk) return fail(GEMM_EUNSUPPORTED, "mode %d has no grouped kernel", mode);
+    int tcount = 0;
+    const KernelCfg *t = configs(mode, &tcount);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t es = (int64_t)elem_size(mode);
+    // A batch of identical problems, enough that the option with fewer tiles
+    // fills every resident-workgroup slot twice (at most 256 problems and
+    // 1 GiB of operands), each with operands of its own.
+    int64_t fewest = INT64_MAX;
+    for (int o = 0; o < 2; ++o) {
+        const KernelCfg &kc = t[gk->cfg_idx[o]];
+        fewest = std::min<int64_t>(fewest, ((m + kc.bm - 1) / kc.bm) * ((n + kc.bn - 1) / kc.bn));
+    }
+    const int64_t slots = (int64_t)num_cus() * std::max(1, gk->wg_per_cu);
+    int64_t count = std::min<int64_t>(256, std::max<int64_t>(1, (2 * slots + fewest - 1) / fewest));
+    const int64_t abytes = (m * k * es + 255) / 256 * 256, bbytes = (k * n * es + 255) / 256 * 256,
+                  cbytes = (m * n * 4 + 255) / 256 * 256;
+    const int64_t per = abytes + bbytes + cbytes;
+    while (count > 1 && count * per > ((int64_t)1 << 30)) count = (count + 1) / 2;
+    uint8_t *buf = nullptr;
+    void *descs = nullptr;
+    int32_t *counters = nullptr;
+    if (hipMalloc(&buf, (size_t)(count * per)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GEMM_ENOMEM, "grouped tuning buffers do not fit");
+    }
+    std::vector<gemm_problem_t> ps((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        gemm_problem_t &p = ps[(size_t)i];
+        memset(&p, 0, sizeof(p));
+        uint8_t *base = buf + i * per;
+        p.mode = mode;
+        p.m = m;
+        p.n = n;
+        p.k = k;
+        p.A = base;
+        p.lda = k;
+        p.B = base + abytes;
+        p.ldb = n;
+        p.C = reinterpret_cast<float *>(base + abytes + bbytes);
+        p.ldc = n;
+        p.scale_a = p.scale_b = 1.f;
+    }
+    int rc = GEMM_OK;
+    // non-zero operands: the clock under load depends on the data
+    if (launch_fill_tuning(buf, count * per / es, (int)es, 3u, s) != hipSuccess)
+        rc = fail(GEMM_EHIP, "filling the tuning operands failed");
+    if (rc == GEMM_OK) rc = alloc_counters(&counters);
+    float batch_ms[2] = {0.f, 0.f}, alone_ms[2] = {0.f, 0.f};
+    for (int o = 0; o < 2 && rc == GEMM_OK; ++o) {
+        GroupPlan plan;
+        rc = build_group_plan(ps.data(), (int32_t)count, plan, o);
+        if (rc != GEMM_OK) break;
+        const size_t bytes = plan.descs.size() * sizeof(GroupDesc);
+        if (descs) (void)hipFree(descs);
+        descs = nullptr;
+        if (hipMalloc(&descs, bytes) != hipSuccess ||
+            hipMemcpy(descs, plan.descs.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(GEMM_EHIP, "grouped tuning descriptors");
+            break;
+        }
+        rc = time_median(s, 7, [&] { return enqueue_group(plan, static_cast<const GroupDesc *>(descs), counters, s); },
+                         &batch_ms[o]);
+        if (rc != GEMM_OK) break;
+        rc = time_median(s, 7, [&] { return enqueue_plain(ps[0], gk->cfg_idx[o], 1, nullptr, s); }, &alone_ms[o]);
+    }
+    if (rc == GEMM_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(GEMM_EHIP, "stream sync failed");
+    if (descs) (void)hipFree(descs);
+    if (counters) (void)hipFree(counters);
+    (void)hipFree(buf);
+    if (rc != GEMM_OK) return rc;
+    tuner_record_grouped(mode, m, n, k, batch_ms[1] < batch_ms[0] ? 1 : 0, alone_ms[1] < alone_ms[0] ? 1 : 0);
+    return GEMM_OK;
+}
+
+int gemm_grouped_info(int32_t mode, int32_t info[4]) {
+    clear_error();
+    if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
+    if (!info) return fail(GEMM_EINVAL, "info is NULL");
+    const GroupedKernel *gk = grouped_kernel(mode);
+    if (!gk) return fail(GEMM_EUNSUPPORTED, "mode %d has no grouped kernel", mode);
+    info[0] = gk->cfg_idx[0];
+    info[1] = gk->cfg_idx[1];
+    info[2] = gk->wg_per_cu;
+    info[3] = gk->lds_bytes;
+    return GEMM_OK;
+}
+
+int gemm_grouped_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t out[3]) {
+    clear_error();
+    if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
+    if (!out) return fail(GEMM_EINVAL, "out is NULL");
+    if (m < 0 || n < 0 || k < 0) return fail(GEMM_EINVAL, "negative dimension");
+    const GroupedKernel *gk = grouped_kernel(mode);
+    if (!gk) return fail(GEMM_EUNSUPPORTED, "mode %d has no grouped kernel", mode);
+    int in_batch = 0, alone = 0;
+    const bool measured = tuner_grouped_choice(mode, m, n, k, &in_batch, &alone);
+    out[0] = gk->cfg_idx[grouped_choose(mode, m, n, k)];
+    out[1] = gk->cfg_idx[grouped_choose_alone(mode, m, n, k)];
+    out[2] = measured ? 1 : 0;
+    return GEMM_OK;
+}
+
+int gemm_grouped_plan(const gemm_problem_t *ps, int32_t count, int32_t *cfg_out) {
+    clear_error();
+    if (count > 0 && !cfg_out) return fail(GEMM_EINVAL, "cfg_out is NULL");
+    GroupPlan plan;
+    int rc = build_group_plan(ps, count, plan);
+    if (rc != GEMM_OK) return rc;
+    for (int i = 0; i < count; ++i) cfg_out[i] = -1;
+    for (size_t j = 0; j < plan.descs.size(); ++j) cfg_out[plan.src[j]] = plan.gk->cfg_idx[plan.descs[j].cfg];
     return GEMM_OK;
 }
 

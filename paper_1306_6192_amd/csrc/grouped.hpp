@@ -10,6 +10,7 @@ struct GroupPlan {
     int mode = 0;
     const GroupedKernel *gk = nullptr;
     std::vector<GroupDesc> descs;   // sorted by descending per-tile cost
+    std::vector<int> src;           // index of each descriptor's problem in the caller's list
     int total_tiles = 0;
     int nwg = 0;
 };
@@ -19,8 +20,9 @@ int grouped_choose(int mode, int64_t m, int64_t n, int64_t k);
 int grouped_choose_alone(int mode, int64_t m, int64_t n, int64_t k);
 
 // Validate the problems (one mode), choose each problem's tile configuration
-// and lay the tiles out; empty outputs are dropped.
-int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan);
+// and lay the tiles out; empty outputs are dropped.  `force` = 0 or 1 puts
+// every problem on that option of the grouped kernel (tuning); -1 chooses.
+int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan, int force = -1);
 
 // Copy the descriptors to the stream's device workspace (stream-ordered).
 int upload_descs(const GroupPlan &plan, hipStream_t s, const GroupDesc **dev_out);

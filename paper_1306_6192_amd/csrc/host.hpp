@@ -55,6 +55,7 @@ int enqueue_plain(const gemm_problem_t &p, int cfg, int split, void *ws, hipStre
 // configuration the problem does not meet is replaced by the any-shape one of
 // the same tile size (both sum every element in the same order).
 bool cfg_eligible(const gemm_problem_t &p, const KernelCfg &kc);
+bool presplit_shape_ok(int64_t n, int64_t k);
 int split_grain(int mode);
 int effective_cfg(const gemm_problem_t &p, int cfg);
 
@@ -64,6 +65,13 @@ int64_t plain_ws_bytes(const gemm_problem_t &p, int cfg, int split);
 // Tuning table.
 void tuner_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg, int *split);
 void heuristic_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg, int *split);
+// floor(log2(d)) (0 for d <= 1): the bucket of a dimension in the tables.
+int dim_bucket(int64_t d);
+// The grouped table's tile options (0 or 1: the grouped kernel's first or
+// second configuration) for the bucket of (m, n, k), in a batch and alone;
+// false when the bucket has not been measured.
+bool tuner_grouped_choice(int mode, int64_t m, int64_t n, int64_t k, int *in_batch, int *alone);
+void tuner_record_grouped(int mode, int64_t m, int64_t n, int64_t k, int in_batch, int alone);
 
 // A device buffer owned by the library that grows on demand.  Growth waits
 // for `s` to drain before freeing the old allocation.

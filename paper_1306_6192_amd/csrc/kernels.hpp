@@ -44,7 +44,8 @@ struct KernelCfg {
 // plain launch of that configuration).
 struct GroupedKernel {
     int cfg_idx[2];
-    int wg_per_cu;
+    int wg_per_cu;             // resident workgroups per CU (launch bound and LDS)
+    int lds_bytes;             // LDS per workgroup
     GroupedLaunchFn launch;
 };
 

@@ -83,6 +83,25 @@ static hipError_t launch_grouped_t(const GroupedArgs &G, int nwg, hipStream_t s)
     return hipGetLastError();
 }
 
+// LDS of a grouped kernel: the larger of its two tiles' rings plus the
+// claimed-tile word.
+template <class Cfg0, class Cfg1>
+constexpr int grouped_lds_bytes() {
+    return cmax<Cfg0::LDS_BYTES, Cfg1::LDS_BYTES>::v + (int)sizeof(int);
+}
+
+// A grouped kernel's table entry: its resident workgroups per CU are the
+// launch bound, capped by what fits in the CU's 160 KiB of LDS.
+template <class Cfg0, class Cfg1, int OCC>
+constexpr GroupedKernel make_grouped(int cfg0, int cfg1) {
+    return GroupedKernel{{cfg0, cfg1},
+                         (160 * 1024 / grouped_lds_bytes<Cfg0, Cfg1>()) < OCC
+                             ? (160 * 1024 / grouped_lds_bytes<Cfg0, Cfg1>())
+                             : OCC,
+                         grouped_lds_bytes<Cfg0, Cfg1>(),
+                         launch_grouped_t<Cfg0, Cfg1, OCC>};
+}
+
 template <class Cfg, int OCC, int CHUNK = 0, int PRESPLIT = 0>
 constexpr KernelCfg make_cfg() {
     return KernelCfg{Cfg::BM, Cfg::BN, Cfg::BK, Cfg::THREADS / 64, Cfg::LDS_BYTES, Cfg::MFMA_K,

@@ -48,7 +48,7 @@ __global__ void presplit_a_kernel(const float *__restrict__ A, int64_t lda, int 
         load8(A, lda, i, 8 * j, k, v);
         u32x4 hi, lo;
         split8(v, hi, lo);
-        uint16_t *row = Ap + (int64_t)i * 3 * k16 + 48 * (j / 2) + 8 * (j % 2);
+        uint16_t *row = Ap + (int64_t)i * 3 * k16 + (int64_t)48 * (j / 2) + 8 * (j % 2);
         *reinterpret_cast<u32x4 *>(row) = lo;
         *reinterpret_cast<u32x4 *>(row + 16) = hi;
         *reinterpret_cast<u32x4 *>(row + 32) = hi;
@@ -72,7 +72,7 @@ __global__ void presplit_b_kernel(const float *__restrict__ B, int64_t ldb, int 
         }
         u32x4 hi, lo;
         split8(v, hi, lo);
-        uint16_t *base = Bp + (int64_t)(48 * (r / 16) + r % 16) * n + 8 * c;
+        uint16_t *base = Bp + ((int64_t)48 * (r / 16) + r % 16) * n + 8 * c;
         *reinterpret_cast<u32x4 *>(base) = hi;
         *reinterpret_cast<u32x4 *>(base + (int64_t)16 * n) = lo;
         *reinterpret_cast<u32x4 *>(base + (int64_t)32 * n) = hi;

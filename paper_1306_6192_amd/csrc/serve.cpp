@@ -58,9 +58,19 @@ struct Slot {
     bool fake_fail = false;
 };
 
-static uint64_t footprint_of(const gemm_problem_t &p) {
+// Device bytes a request holds while in flight: its operands and output,
+// plus, under the plain-launch executor, the workspace its plain launch uses
+// (split-K partial slabs, split-BF16x3 operand copies).  Grouped launches use
+// no workspace.
+static uint64_t footprint_of(const gemm_problem_t &p, int executor) {
     const uint64_t es = elem_size(p.mode);
-    return (uint64_t)p.m * p.k * es + (uint64_t)p.k * p.n * es + (uint64_t)p.m * p.n * 4;
+    uint64_t fp = (uint64_t)p.m * p.k * es + (uint64_t)p.k * p.n * es + (uint64_t)p.m * p.n * 4;
+    if (executor == 2 && p.m > 0 && p.n > 0 && p.k > 0) {
+        int c = 0, sp = 1;
+        tuner_choose(p.mode, p.m, p.n, p.k, &c, &sp);
+        fp += (uint64_t)plain_ws_bytes(p, c, sp);
+    }
+    return fp;
 }
 
 struct Server {
@@ -317,7 +327,7 @@ int gemm_serve_footprint(const gemm_problem_t *p, uint64_t *bytes_out) {
     if (!bytes_out) return fail(GEMM_EINVAL, "bytes_out is NULL");
     int rc = validate(p);
     if (rc != GEMM_OK) return rc;
-    *bytes_out = footprint_of(*p);
+    *bytes_out = footprint_of(*p, 0);
     return GEMM_OK;
 }
 
@@ -352,7 +362,7 @@ int gemm_serve_submit(void *server, const gemm_problem_t *p, uint64_t t_arrival_
     Server *s = static_cast<Server *>(server);
     int rc = validate(p);
     if (rc != GEMM_OK) return rc;
-    const uint64_t fp = footprint_of(*p);
+    const uint64_t fp = footprint_of(*p, s->cfg.executor);
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->sticky != GEMM_OK) return fail(s->sticky, "server is in a failed state");
     if (s->stop) return fail(GEMM_EINVAL, "server is shutting down");

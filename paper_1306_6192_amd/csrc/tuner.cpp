@@ -1,8 +1,12 @@
-// Tile-configuration autotuner: a shape-keyed table of (config, split-K)
-// choices, filled by measurement (gemm_tune) or by a cost model when a shape
-// has not been measured.  The choice depends on (mode, m, n, k) only, never
-// on load, so a shape gets the same configuration -- and therefore the same
-// summation order -- on every path.
+// Tile-configuration autotuner: tables of (config, split-K) choices for plain
+// launches and of tile choices for grouped launches, filled by measurement on
+// the device (gemm_tune, gemm_tune_bucket, gemm_tune_grouped) and consulted
+// before a cost model.  Plain choices are keyed by the exact (mode, m, n, k)
+// or, failing that, by its log2 bucket (floor(log2) of each dimension), so
+// shapes never measured still get a measured choice of a neighbouring shape;
+// grouped choices are keyed by bucket.  Every choice depends on (mode, m, n,
+// k) only, never on load, so a shape gets the same configuration -- and
+// therefore the same summation order -- on every path.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -18,10 +22,26 @@
 namespace mg {
 
 typedef std::tuple<int, int64_t, int64_t, int64_t> Key;
+typedef std::tuple<int, int, int, int> BKey;   // mode, log2 buckets of m, n, k
 
 static std::mutex g_mu;
-static std::map<Key, std::pair<int, int>> g_table;
+static std::map<Key, std::pair<int, int>> g_table;          // exact shape -> (cfg, split)
+static std::map<BKey, std::pair<int, int>> g_plain_bucket;  // bucket -> (cfg, split)
+static std::map<BKey, std::pair<int, int>> g_grouped;       // bucket -> (option in a batch, option alone)
 static bool g_env_loaded = false;
+
+int dim_bucket(int64_t d) {
+    int b = 0;
+    while (d > 1) {
+        d >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+static BKey bucket_of(int mode, int64_t m, int64_t n, int64_t k) {
+    return BKey(mode, dim_bucket(m), dim_bucket(n), dim_bucket(k));
+}
 
 static int load_file_locked(const char *path);
 
@@ -52,7 +72,7 @@ void heuristic_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg_out, i
         // tile's rate at 8192^3 (measured; the complex 128x128 one beats the
         // register-staged 256x128 one although tile_eff favours the latter)
         if (kc.chunk && (k % kc.chunk || n % kc.chunk)) continue;
-        if (kc.presplit && n % 8) continue;
+        if (kc.presplit && !presplit_shape_ok(n, k)) continue;
         // the pre-split split-BF16x3 path runs at about 1.75x the register-
         // staged split tile at 8192^3 (its operands are split once, not once
         // per output tile)
@@ -84,40 +104,87 @@ void heuristic_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg_out, i
     }
 }
 
+static void load_env_locked() {
+    if (g_env_loaded) return;
+    g_env_loaded = true;
+    const char *env = getenv("MI355GEMM_TUNE_FILE");
+    if (env && *env) (void)load_file_locked(env);
+}
+
 void tuner_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg, int *split) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        if (!g_env_loaded) {
-            g_env_loaded = true;
-            const char *env = getenv("MI355GEMM_TUNE_FILE");
-            if (env && *env) (void)load_file_locked(env);
-        }
+        load_env_locked();
         auto it = g_table.find(Key(mode, m, n, k));
         if (it != g_table.end()) {
             *cfg = it->second.first;
             *split = it->second.second;
             return;
         }
+        auto ib = g_plain_bucket.find(bucket_of(mode, m, n, k));
+        if (ib != g_plain_bucket.end()) {
+            *cfg = ib->second.first;
+            *split = ib->second.second;
+            return;
+        }
     }
     heuristic_choose(mode, m, n, k, cfg, split);
 }
 
+bool tuner_grouped_choice(int mode, int64_t m, int64_t n, int64_t k, int *in_batch, int *alone) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_env_locked();
+    auto it = g_grouped.find(bucket_of(mode, m, n, k));
+    if (it == g_grouped.end()) return false;
+    *in_batch = it->second.first;
+    *alone = it->second.second;
+    return true;
+}
+
+void tuner_record_grouped(int mode, int64_t m, int64_t n, int64_t k, int in_batch, int alone) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_grouped[bucket_of(mode, m, n, k)] = {in_batch, alone};
+}
+
+// One JSON object per line, in one of three forms (the forms gemm_tuner_save
+// writes; lines in any other form are skipped):
+//   {"mode": M, "m": m, "n": n, "k": k, "cfg": C, "split": S}
+//   {"bucket": "plain", "mode": M, "bm": a, "bn": b, "bk": c, "cfg": C, "split": S}
+//   {"bucket": "grouped", "mode": M, "bm": a, "bn": b, "bk": c, "tile": T, "alone": U}
 static int load_file_locked(const char *path) {
     FILE *f = fopen(path, "r");
     if (!f) return fail(GEMM_ENOTFOUND, "cannot open tuning file %s", path);
     char line[512];
     int n_ok = 0;
     while (fgets(line, sizeof(line), f)) {
-        int mode, cfg, split;
+        int mode, cfg, split, bm, bn, bk;
         long long m, n, k;
+        int count = 0;
         if (sscanf(line, " {\"mode\": %d, \"m\": %lld, \"n\": %lld, \"k\": %lld, \"cfg\": %d, \"split\": %d",
                    &mode, &m, &n, &k, &cfg, &split) == 6) {
-            int count = 0;
+            if (!mode_known(mode)) continue;
             configs(mode, &count);
-            if (mode_known(mode) && cfg >= 0 && cfg < count && split >= 1) {
+            if (cfg >= 0 && cfg < count && split >= 1) {
                 g_table[Key(mode, m, n, k)] = {cfg, split};
                 ++n_ok;
             }
+        } else if (sscanf(line,
+                          " {\"bucket\": \"plain\", \"mode\": %d, \"bm\": %d, \"bn\": %d, \"bk\": %d, "
+                          "\"cfg\": %d, \"split\": %d",
+                          &mode, &bm, &bn, &bk, &cfg, &split) == 6) {
+            if (!mode_known(mode)) continue;
+            configs(mode, &count);
+            if (cfg >= 0 && cfg < count && split >= 1) {
+                g_plain_bucket[BKey(mode, bm, bn, bk)] = {cfg, split};
+                ++n_ok;
+            }
+        } else if (sscanf(line,
+                          " {\"bucket\": \"grouped\", \"mode\": %d, \"bm\": %d, \"bn\": %d, \"bk\": %d, "
+                          "\"tile\": %d, \"alone\": %d",
+                          &mode, &bm, &bn, &bk, &cfg, &split) == 6) {
+            if (!mode_known(mode) || cfg < 0 || cfg > 1 || split < 0 || split > 1) continue;
+            g_grouped[BKey(mode, bm, bn, bk)] = {cfg, split};
+            ++n_ok;
         }
     }
     fclose(f);
@@ -184,12 +251,31 @@ int gemm_tuner_save(const char *path) {
                 std::get<0>(kv.first), (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
                 (long long)std::get<3>(kv.first), kv.second.first, kv.second.second);
     }
+    for (auto &kv : g_plain_bucket)
+        fprintf(f,
+                "{\"bucket\": \"plain\", \"mode\": %d, \"bm\": %d, \"bn\": %d, \"bk\": %d, \"cfg\": %d, "
+                "\"split\": %d}\n",
+                std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                kv.second.first, kv.second.second);
+    for (auto &kv : g_grouped)
+        fprintf(f,
+                "{\"bucket\": \"grouped\", \"mode\": %d, \"bm\": %d, \"bn\": %d, \"bk\": %d, \"tile\": %d, "
+                "\"alone\": %d}\n",
+                std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                kv.second.first, kv.second.second);
     fclose(f);
     return GEMM_OK;
 }
 
-int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream) {
-    clear_error();
+}  // extern "C"
+
+namespace mg {
+
+// Time every legal (configuration, split) of one shape; *cfg_out gets the
+// fastest, *split_out its requested split factor and *norm_split_out the
+// factor make_launch normalises it to for this shape.
+static int tune_plain(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream, int *cfg_out, int *split_out,
+                      int *norm_split_out) {
     if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
     if (m <= 0 || n <= 0 || k <= 0) return fail(GEMM_EINVAL, "tuning needs a non-empty product");
     int count = 0;
@@ -218,7 +304,7 @@ int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream) {
         (void)hipGetLastError();
         rc = fail(GEMM_ENOMEM, "tuning buffers do not fit");
     }
-    int best_c = 0, best_s = 1;
+    int best_c = 0, best_s = 1, best_req = 1;
     float best_ms = 1e30f;
     struct Cand {
         int cfg, split;
@@ -268,6 +354,7 @@ int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream) {
             if (c.ms < best_ms) {
                 best_ms = c.ms;
                 best_c = c.cfg;
+                best_req = c.split;
                 best_s = make_launch(p, t[c.cfg], c.split).splits;
             }
     }
@@ -276,8 +363,33 @@ int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream) {
     if (C) (void)hipFree(C);
     if (ws) (void)hipFree(ws);
     if (rc != GEMM_OK) return rc;
+    *cfg_out = best_c;
+    *split_out = best_req;
+    *norm_split_out = best_s;
+    return GEMM_OK;
+}
+
+}  // namespace mg
+
+extern "C" {
+
+int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream) {
+    clear_error();
+    int cfg = 0, req = 1, split = 1;
+    const int rc = tune_plain(mode, m, n, k, stream, &cfg, &req, &split);
+    if (rc != GEMM_OK) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_table[Key(mode, m, n, k)] = {best_c, best_s};
+    g_table[Key(mode, m, n, k)] = {cfg, split};
+    return GEMM_OK;
+}
+
+int gemm_tune_bucket(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream) {
+    clear_error();
+    int cfg = 0, req = 1, split = 1;
+    const int rc = tune_plain(mode, m, n, k, stream, &cfg, &req, &split);
+    if (rc != GEMM_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plain_bucket[bucket_of(mode, m, n, k)] = {cfg, req};
     return GEMM_OK;
 }
 

@@ -125,3 +125,35 @@ def test_plain_executor_equals_gemm_plain():
         got = host(r["C"]).copy()
         ref = host(mg.gemm(r["a"], r["b"], mode=r["mode"], scale_a=r["sa"], scale_b=r["sb"]))
         assert np.array_equal(got, ref)
+
+
+def test_plain_executor_admits_by_footprint_plus_workspace():
+    """Under the plain-launch executor a request holds its operands, its
+    output and its plain launch's split-K workspace: a budget one byte short
+    of that sum refuses it, the sum itself admits it."""
+    log("serve plain executor footprint")
+    m, n, k = 128, 8192, 8192
+    A, B = synth.pair(m, n, k, seed=14)
+    a, b = dev(A), dev(B)
+    C = torch.full((m, n), float("nan"), device="cuda")
+    p = mg.make_problem(a, b, C, mg.MODE_F32)
+    lib = _lib.load()
+    base, ws = ctypes.c_uint64(), ctypes.c_uint64()
+    _lib.check(lib.gemm_serve_footprint(ctypes.byref(p), ctypes.byref(base)))
+    _lib.check(lib.gemm_plain_workspace_bytes(ctypes.byref(p), ctypes.byref(ws)))
+    assert base.value == 4 * (m * k + k * n + m * n)
+    assert ws.value > 0                  # the tuned launch splits k
+    cfg = dict(max_inflight=4, num_streams=1, max_batch=1, queue_capacity=16, executor=2, fake_fail_every=0)
+    for budget, ok in ((base.value + ws.value - 1, False), (base.value + ws.value, True)):
+        h = ctypes.c_void_p()
+        assert lib.gemm_serve_create(ctypes.byref(_lib.ServeConfig(hbm_budget_bytes=budget, **cfg)),
+                                     ctypes.byref(h)) == 0
+        t = ctypes.c_uint64()
+        rc = lib.gemm_serve_submit(h, ctypes.byref(p), 0, ctypes.byref(t))
+        assert rc == (0 if ok else _lib.GEMM_ENOMEM), (budget, rc)
+        assert lib.gemm_serve_drain(h) == 0
+        if ok:
+            r = _lib.ServeResult()
+            assert lib.gemm_serve_poll(h, t, ctypes.byref(r)) == 0
+        assert lib.gemm_serve_destroy(h) == 0
+    assert np.array_equal(host(C), host(mg.gemm(a, b)))
