@@ -6,29 +6,35 @@ step = one product of each shape (m, n, k) in {2048^3, 4096^3, 8192^3,
 inputs resident in HBM before the timed region; value = aggregate TFLOP/s
 (2mnk flops per product).  The roofline object is for the dominant launch
 (8192^3), timed with HIP events on the stream it runs on.  Every shape's
-sampled normwise error against float64 dot products of the same inputs is
-reported, and the oracle (the binary64 reference loop) is timed on the
-host's cores on a bounded sample.
+normwise error against the oracle (the binary64 reference loop) over the
+whole output is reported: the oracle leg computes each input's full binary64
+product on the host's cores (the 8192^3 one is the timed CPU baseline), and
+the device comparison reduction (gemm_errnorm) takes the error against it.
+A single-thread oracle run of 4096^3 gives the row comparable with the
+paper's sequential CPU timings.
 
 Secondary sections (extra keys of the same line; --sections to choose):
   precision  m = n = k = 8192, N(0,1) and wide-range inputs: BF16, F16, FP8
              E4M3 (per-tensor scale) and split-BF16x3, TFLOP/s, fraction of
-             the dtype's MFMA peak, sampled error vs float64 products of the
-             float32 inputs and of the quantised operands.
+             the dtype's MFMA peak, normwise error vs the oracle of the
+             float32 inputs over the whole output, and sampled error vs
+             float64 products of the quantised operands.
   grouped    512 problems, m, n, k log-uniform in [32, 1024] (seed 0), FP32
              and BF16 in / FP32 out: one captured persistent launch vs 512
              plain launches.
-  serving    Poisson arrivals of products with m, n, k log-uniform in
+  serving    10,000 requests, Poisson arrivals, m, n, k log-uniform in
              [64, 4096], 50% FP32 / 35% BF16 / 15% E4M3, operands resident
              in HBM; p50/p99 latency and aggregate TFLOP/s per arrival rate,
-             continuous batching vs plain FIFO launches.
+             rates swept past the point where p99 diverges, continuous
+             batching vs plain FIFO launches, and one run whose HBM budget
+             binds admission.
   ablation   the paper's global-memory and 16x16-LDS kernels beside the
              matrix-core kernel, float 4096^3.
   table2     the double and complex-float products at 4096^3 and 8192^3.
   addition   float and double matrix addition/subtraction at 4096^2.
-  vendor     context: the vendor GEMM library through PyTorch (torch.matmul,
-             torch._scaled_mm) on the same shapes, with its sampled error and
-             the ratio ours / vendor.
+  vendor     (not in the default set) context: the vendor GEMM library
+             through PyTorch (torch.matmul, torch._scaled_mm) on the same
+             shapes, with its sampled error and the ratio ours / vendor.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections plain,precision,grouped,serving,...]
 """
@@ -56,12 +62,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--sections", default="plain,precision,grouped,serving,ablation,table2,addition,vendor")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--sections", default="plain,precision,grouped,serving,ablation,table2,addition")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and full-output errors against the oracle)")
+    ap.add_argument("--no-single-thread", action="store_true", help="skip the single-thread 4096^3 oracle run")
     ap.add_argument("--samples", type=int, default=512, help="sampled outputs per product for the error")
-    ap.add_argument("--serve-requests", type=int, default=4000)
-    ap.add_argument("--serve-rates", default="4000,16000,64000")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-rates", default="4000,16000,64000,128000,256000")
+    ap.add_argument("--serve-tight-budget-gib", type=float, default=1.0,
+                    help="HBM budget of the extra serving run whose admission binds")
+    ap.add_argument("--serve-tight-rate", type=float, default=64000.0)
     ap.add_argument("--precision-modes", default="bf16,f16,e4m3,split_bf16x3")
     ap.add_argument("--precision-dists", default="normal,wide")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy (section copy)")
@@ -124,29 +134,65 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(A, B, target_s: float):
-    """The oracle (binary64 loop, all host threads) on whole rows of the
-    8192^3 product, enough rows for about `target_s` seconds."""
+class OracleJobs:
+    """Device outputs waiting for their full-output error against the oracle,
+    keyed by the input that produced them: (m, n, k, seed, dist) ->
+    [(record, float32 device C)].  The oracle leg fills each record's
+    rel_err_vs_oracle_full."""
+
+    def __init__(self):
+        self.jobs = {}
+
+    def add(self, key, rec, dC):
+        self.jobs.setdefault(tuple(key), []).append((rec, dC))
+
+
+def oracle_leg(args, torch, mg, synth, stream, jobs, line):
+    """The oracle (binary64 loop) on the host's cores: the full product of
+    every input a section registered, timed (the 8192^3 uniform product is
+    the CPU baseline), and each registered device output's normwise error
+    against it from the device comparison reduction; then one single-thread
+    4096^3 product, the row comparable with the paper's sequential CPU
+    timings (which are float and double products on one core)."""
     import oracle
     threads = oracle.default_threads()
-    B64 = np.ascontiguousarray(B, dtype=np.float64)
-    m, k = A.shape
-    n = B.shape[1]
-    rows = threads
-    t0 = time.perf_counter()
-    oracle.gemm(A[:rows].astype(np.float64), B64, threads)
-    dt = time.perf_counter() - t0
-    total_rows, total_t = rows, dt
-    more = int(max(0, (target_s - dt) / max(dt, 1e-9) * rows))
-    more = min(more, m - rows) // threads * threads
-    if more > 0:
+    base = None
+    runs = []
+    for key in sorted(jobs.jobs, key=lambda t: -(t[0] * t[1] * t[2])):
+        m, n, k, seed, dist = key
+        A, B = synth.pair(m, n, k, seed=seed, dist=dist)
         t0 = time.perf_counter()
-        oracle.gemm(A[rows:rows + more].astype(np.float64), B64, threads)
-        total_t += time.perf_counter() - t0
-        total_rows += more
-    flops = 2.0 * total_rows * n * k
-    return {"value": flops / total_t / 1e12, "unit": "TFLOP/s", "cores": threads, "cpu": cpu_model(), "kind": "oracle",
-            "sample": f"{total_rows} full rows of the {m}x{n}x{k} product (binary64 loop), {total_t:.1f} s"}
+        R = oracle.gemm(A, B, threads)
+        dt = time.perf_counter() - t0
+        runs.append({"m": m, "n": n, "k": k, "dist": dist, "seconds": round(dt, 2),
+                     "tflops": round(2.0 * m * n * k / dt / 1e12, 4)})
+        if (m, n, k, dist) == (8192, 8192, 8192, "uniform"):
+            base = (2.0 * m * n * k / dt / 1e12, dt)
+        dR = torch.from_numpy(R).cuda()
+        for rec, dC in jobs.jobs[key]:
+            e = mg.errnorm(dC, dR, stream=stream).cpu().numpy()
+            rec["rel_err_vs_oracle_full"] = float(np.sqrt(e[0] / e[1])) if e[1] > 0 else float(np.sqrt(e[0]))
+            rec["max_abs_err_vs_oracle"] = float(e[2])
+        log(f"oracle {runs[-1]}")
+        del dR, R
+        torch.cuda.empty_cache()
+    cb = {"value": None, "unit": "TFLOP/s", "cores": threads, "cpu": cpu_model(), "kind": "oracle",
+          "sample": None, "full_products": runs}
+    if base is not None:
+        cb["value"] = round(base[0], 5)
+        cb["sample"] = (f"the whole 8192x8192x8192 product of the plain workload (binary64 loop, {threads} threads), "
+                        f"{base[1]:.1f} s")
+    if not args.no_single_thread:
+        A, B = synth.pair(4096, 4096, 4096, seed=0)
+        t0 = time.perf_counter()
+        oracle.gemm(A, B, 1)
+        dt = time.perf_counter() - t0
+        cb["single_thread_4096"] = {
+            "cores": 1, "seconds": round(dt, 2), "gflops": round(2.0 * 4096 ** 3 / dt / 1e9, 3),
+            "note": "binary64 loop, one thread; the paper's sequential 4096^3 products took 991.96 s (float) and "
+                    "1455.27 s (double) on a Xeon E7-4860, 856.9 s and 1017.96 s on a Core i7 950"}
+        log(f"oracle single thread {cb['single_thread_4096']}")
+    line["cpu_baseline"] = cb
 
 
 # Device time each secondary measurement runs before its timed calls.
@@ -186,7 +232,7 @@ class Timer:
 
 
 # ---------------------------------------------------------------------------
-def section_plain(args, torch, mg, synth, stream, line):
+def section_plain(args, torch, mg, synth, stream, line, jobs):
     dev = torch.device("cuda:0")
     data = []
     for (m, n, k) in SHAPES:
@@ -240,6 +286,7 @@ def section_plain(args, torch, mg, synth, stream, line):
                           "alg_hbm_gb_per_s": round(4.0 * (m * k + k * n + m * n) / (avg / 1e3) / 1e9, 1),
                           "cfg": mg.config_info(mg.MODE_F32, cfg), "split_k": split,
                           "rel_err_sampled": relerr(C[rows, cols], R)})
+        jobs.add((m, n, k, 0, "uniform"), per_shape[-1], dC)
         if (m, n, k) == DOMINANT:
             info = mg.config_info(mg.MODE_F32, cfg)
             kind = "asynchronous-copy" if mg.config_chunk(mg.MODE_F32, cfg) > 0 else "register-staged"
@@ -263,16 +310,13 @@ def section_plain(args, torch, mg, synth, stream, line):
     c5 = torch.empty((512, 512), dtype=torch.float32, device=dev)
     ms5 = float(np.median(Timer(torch, stream).time(lambda: mg.gemm(d5a, d5b, out=c5, stream=stream), 100, warmup=3)))
     line["c1_512"] = {"ms_median": round(ms5, 5), "tflops": round(2 * 512 ** 3 / (ms5 / 1e3) / 1e12, 2),
-                      "rel_err": relerr(c5.cpu().numpy(), A5.astype(np.float64) @ B5.astype(np.float64))}
-    if not args.no_cpu_baseline:
-        A, B = data[SHAPES.index(DOMINANT)][:2]
-        line["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
+                      "rel_err_vs_numpy_f64": relerr(c5.cpu().numpy(), A5.astype(np.float64) @ B5.astype(np.float64))}
+    jobs.add((512, 512, 512, 0, "uniform"), line["c1_512"], c5)
     del data
-    torch.cuda.empty_cache()
 
 
 # ---------------------------------------------------------------------------
-def section_precision(args, torch, mg, synth, stream, line):
+def section_precision(args, torch, mg, synth, stream, line, jobs):
     T = Timer(torch, stream)
     m = n = k = 8192
     out = []
@@ -280,7 +324,6 @@ def section_precision(args, torch, mg, synth, stream, line):
     for dist in args.precision_dists.split(","):
         A, B = synth.pair(m, n, k, seed=0, dist=dist)
         dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
-        C = torch.empty((m, n), device="cuda")
         g = synth.rng(77)
         rows = g.integers(0, m, size=args.samples)
         cols = g.integers(0, n, size=args.samples)
@@ -306,6 +349,7 @@ def section_precision(args, torch, mg, synth, stream, line):
                 sa, sb = float(s1.cpu()[0]), float(s2.cpu()[0])
             else:
                 a, b, sa, sb = dA, dB, 1.0, 1.0
+            C = torch.empty((m, n), device="cuda")   # kept for the full-output error
             # warm-up launches first: the clock settles at its sustained level
             # under matrix-core load only after a few milliseconds
             ms = T.time(lambda: mg.gemm(a, b, out=C, mode=mode, scale_a=sa, scale_b=sb, stream=stream), 10, warmup=3,
@@ -326,9 +370,10 @@ def section_precision(args, torch, mg, synth, stream, line):
             cfg, split = mg.tuner_lookup(mode, m, n, k)
             rec["cfg"] = mg.config_info(mode, cfg)
             out.append(rec)
+            jobs.add((m, n, k, 0, dist), rec, C)
             log(f"precision {rec}")
             del a, b
-        del dA, dB, C
+        del dA, dB
         torch.cuda.empty_cache()
     line["precision_8192"] = out
 
@@ -359,7 +404,7 @@ def secondary_sampled(torch, A, B, rows, cols, mode, sa, sb):
 
 
 # ---------------------------------------------------------------------------
-def section_grouped(args, torch, mg, synth, stream, line):
+def section_grouped(args, torch, mg, synth, stream, line, jobs=None):
     T = Timer(torch, stream)
     probs = synth.grouped_problems(512, 32, 1024, seed=0)
     flops = sum(2.0 * A.shape[0] * B.shape[1] * A.shape[1] for A, B in probs)
@@ -426,7 +471,7 @@ def section_grouped(args, torch, mg, synth, stream, line):
 
 
 # ---------------------------------------------------------------------------
-def section_serving(args, torch, mg, synth, stream, line):
+def section_serving(args, torch, mg, synth, stream, line, jobs=None):
     from paper_1306_6192_amd import _lib
     lib = _lib.load()
     N = args.serve_requests
@@ -444,8 +489,11 @@ def section_serving(args, torch, mg, synth, stream, line):
     s8 = float(s8.cpu()[0])
     esz = {mg.MODE_F32: 4, mg.MODE_BF16: 2, mg.MODE_F8E4M3: 1}
     base = {mg.MODE_F32: pool32.data_ptr(), mg.MODE_BF16: pool16.data_ptr(), mg.MODE_F8E4M3: pool8.data_ptr()}
-    # output arena: consecutive requests take consecutive regions (ring)
-    arena_bytes = 24 << 30
+    # output arena: every request has a region of its own (34.9 GiB for the
+    # 10,000-request trace), so outputs stay for the error check; a ring only
+    # when a longer trace would not fit
+    need_c = int(sum((int(m) * int(n) * 4 + 255) // 256 * 256 for m, n, _ in dims))
+    arena_bytes = min(need_c, 48 << 30)
     arena = torch.empty(arena_bytes // 4, dtype=torch.float32, device="cuda")
     budget = 8 << 30
     probs, flops, where = [], 0.0, []
@@ -464,21 +512,24 @@ def section_serving(args, torch, mg, synth, stream, line):
         flops += 2.0 * m * n * k
     arr = _lib.problems_array(probs)
     out = {"requests": N, "total_tflop": round(flops / 1e12, 3), "budget_gb": budget / 2**30, "rates": []}
-    for rate in [float(r) for r in args.serve_rates.split(",")]:
+    runs = [(float(r), budget) for r in args.serve_rates.split(",")]
+    runs.append((args.serve_tight_rate, int(args.serve_tight_budget_gib * 2**30)))
+    for rate, run_budget in runs:
         offs = (synth.poisson_arrivals(N, rate, seed=3) * 1e9).astype(np.uint64)
         for executor, label in ((0, "batched"), (2, "plain_fifo")):
-            cfg = _lib.ServeConfig(budget, 256, 4, 64, 1 << 20, executor, 0)
+            cfg = _lib.ServeConfig(run_budget, 256, 4, 64, 1 << 20, executor, 0)
             h = ctypes.c_void_p()
             _lib.check(lib.gemm_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
             tickets = (ctypes.c_uint64 * N)()
             _lib.check(lib.gemm_serve_replay(h, arr, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), N,
                                              tickets))
             _lib.check(lib.gemm_serve_drain(h))
-            lat, t_first, t_last, bs = [], None, 0, []
+            lat, t_first, t_last, bs, admit_wait = [], None, 0, [], []
             for i in range(N):
                 r = _lib.ServeResult()
                 _lib.check(lib.gemm_serve_poll(h, tickets[i], ctypes.byref(r)))
                 lat.append((r.t_done_ns - r.t_arrival_ns) / 1e6)
+                admit_wait.append((r.t_admit_ns - r.t_arrival_ns) / 1e6)
                 t_first = r.t_arrival_ns if t_first is None else min(t_first, r.t_arrival_ns)
                 t_last = max(t_last, r.t_done_ns)
                 bs.append(r.batch_size)
@@ -486,10 +537,13 @@ def section_serving(args, torch, mg, synth, stream, line):
             lib.gemm_serve_stats(h, ctypes.byref(st))
             _lib.check(lib.gemm_serve_destroy(h))
             lat = np.array(lat)
-            rec = {"rate_per_s": rate, "executor": label, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            rec = {"rate_per_s": rate, "executor": label, "budget_gb": round(run_budget / 2**30, 3),
+                   "p50_ms": round(float(np.percentile(lat, 50)), 3),
                    "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
                    "tflops": round(flops / ((t_last - t_first) / 1e9) / 1e12, 2),
+                   "offered_tflops": round(flops / (float(offs[-1]) / 1e9) / 1e12, 2) if offs[-1] > 0 else None,
                    "mean_batch": round(float(np.mean(bs)), 2),
+                   "mean_admit_wait_ms": round(float(np.mean(admit_wait)), 3),
                    "peak_inflight_gb": round(st.peak_inflight_bytes / 2**30, 3)}
             out["rates"].append(rec)
             log(f"serving {rec}")
@@ -519,7 +573,7 @@ def section_serving(args, torch, mg, synth, stream, line):
     torch.cuda.empty_cache()
 
 
-def section_ablation(args, torch, mg, synth, stream, line):
+def section_ablation(args, torch, mg, synth, stream, line, jobs=None):
     """The paper's own comparison at its size (m = n = k = 4096, float):
     global-memory kernel vs 16x16 shared-memory kernel (Listings 3 and 4,
     Table 2 / Fig. 8), rebuilt for gfx950, beside the matrix-core kernel."""
@@ -546,7 +600,7 @@ def section_ablation(args, torch, mg, synth, stream, line):
                              "paper_table2_c2050_seconds": {"global_memory": 2.49, "shared_memory": 0.83}}
 
 
-def section_table2(args, torch, mg, synth, stream, line):
+def section_table2(args, torch, mg, synth, stream, line, jobs=None):
     """The paper's Table 2 columns at its size, m = n = k = 4096 (plus 8192^3):
     the double product (binary64 MFMA) and the complex-float product (four
     real FP32 MFMA products per complex term), seconds, TFLOP/s and the
@@ -589,7 +643,7 @@ def section_table2(args, torch, mg, synth, stream, line):
                                                                    "complex_float": 2.07}}
 
 
-def section_addition(args, torch, mg, synth, stream, line):
+def section_addition(args, torch, mg, synth, stream, line, jobs=None):
     """Matrix addition and subtraction at the paper's size (4096 x 4096,
     float and double; Results section, Fig. 9): device time, HBM GB/s (three
     streams of the element size) against 8 TB/s, and the host CPU time one
@@ -629,7 +683,7 @@ def section_addition(args, torch, mg, synth, stream, line):
     line["addition_4096"] = res
 
 
-def section_vendor(args, torch, mg, synth, stream, line):
+def section_vendor(args, torch, mg, synth, stream, line, jobs=None):
     """Context, not part of the product: the vendor GEMM library as PyTorch
     calls it (torch.matmul, torch._scaled_mm for FP8) on the same shapes and
     inputs, timed the same way, with its sampled error against float64 dot
@@ -701,7 +755,7 @@ def section_vendor(args, torch, mg, synth, stream, line):
     line["vendor_library_context"] = out
 
 
-def section_copy(args, torch, mg, synth, stream, line):
+def section_copy(args, torch, mg, synth, stream, line, jobs=None):
     """A plain device copy of known size: the reference for scaling the
     FETCH_SIZE / WRITE_SIZE counters of the product kernels."""
     n = args.copy_mib << 18          # float32 elements
@@ -737,12 +791,19 @@ def main():
                                "(8192,1024,4096), (128,8192,8192), row-major",
                    "parallelism": "single GPU"},
     }
+    jobs = OracleJobs()
     for name in sections:
         log(f"section {name}")
         {"plain": section_plain, "precision": section_precision, "grouped": section_grouped,
          "serving": section_serving, "copy": section_copy, "ablation": section_ablation,
          "table2": section_table2, "addition": section_addition,
-         "vendor": section_vendor}[name](args, torch, mg, synth, stream, line)
+         "vendor": section_vendor}[name](args, torch, mg, synth, stream, line, jobs)
+    if not args.no_cpu_baseline:
+        log("oracle leg")
+        oracle_leg(args, torch, mg, synth, stream, jobs, line)
+        errs = [p.get("rel_err_vs_oracle_full") for p in line.get("per_shape", [])]
+        if errs and all(e is not None for e in errs):
+            line["max_rel_err_vs_oracle_full"] = max(errs)
     print(json.dumps(line), flush=True)
 
 
