@@ -131,6 +131,23 @@ int gemm_plain_cfg(const gemm_problem_t *p, int32_t cfg, int32_t split_k, void *
  * count. */
 int gemm_plain_workspace_bytes(const gemm_problem_t *p, uint64_t *bytes_out);
 
+/* Allocation-free plain product, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same tile configuration, split-K factor and bits as
+ * gemm_plain; the workspace gemm_plain_workspace_bytes reports comes from a
+ * fixed device array of GEMM_NOALLOC_SCRATCH_BYTES that each GPU holds from
+ * the library's load until the process ends, instead of the per-stream
+ * workspace.  No call allocates or frees device memory (the first call on a
+ * device looks the array's address up once).  Errors: as gemm_plain, plus
+ * GEMM_EINVAL when the product needs more workspace than the array holds
+ * (gemm_plain serves it).  Every call on one GPU shares that GPU's array:
+ * calls whose work overlaps on the device (different streams, or several
+ * host threads without ordering) race and give undefined results; calls on
+ * one stream are ordered by it.  Nothing in the array needs to start at
+ * zero (every slab element is written before it is read). */
+#define GEMM_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+int gemm_plain_noalloc(const gemm_problem_t *p, void *stream);
+
 /* The paper's own GPU kernels on gfx950, float32 only, as a baseline for the
  * matrix-core path: variant 0 = one thread per c_ij reading A and B from
  * global memory (Implementation section, Listing 3); variant 1 = 16x16

@@ -24,6 +24,7 @@ GEMM_EHIP = -4
 GEMM_EBUSY = -5
 GEMM_ENOTFOUND = -6
 GEMM_EINTERNAL = -7
+NOALLOC_SCRATCH_BYTES = 64 << 20   # GEMM_NOALLOC_SCRATCH_BYTES
 
 MODE_F32 = 0
 MODE_BF16 = 1
@@ -77,6 +78,7 @@ _SIGS = {
     "gemm_plain": (c_int32, [_P, c_void_p]),
     "gemm_plain_cfg": (c_int32, [_P, c_int32, c_int32, c_void_p]),
     "gemm_plain_workspace_bytes": (c_int32, [_P, POINTER(c_uint64)]),
+    "gemm_plain_noalloc": (c_int32, [_P, c_void_p]),
     "gemm_ablation": (c_int32, [_P, c_int32, c_void_p]),
     "gemm_plain_f64": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
                                  c_int64, c_void_p]),

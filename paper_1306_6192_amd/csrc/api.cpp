@@ -294,6 +294,40 @@ std::unique_lock<std::mutex> lock_stream_workspaces(hipStream_t s) {
     return std::unique_lock<std::mutex>(stream_ws(s)->mu);
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of gemm_plain_noalloc: split-K partial slabs and split-BF16x3
+// operand copies of at most GEMM_NOALLOC_SCRATCH_BYTES, in a device array that
+// every GPU the library runs on holds until the process ends.  Host code never
+// passes the array's name to a kernel or a copy (on the host it is only a
+// stand-in for the symbol): it uses the per-device address
+// hipGetSymbolAddress returns, taken once per device with that device
+// current.
+static __device__ __align__(256) uint8_t scratch[GEMM_NOALLOC_SCRATCH_BYTES];
+
+static const int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices];
+
+int noalloc_scratch(void **out) {
+    *out = nullptr;
+    int dev = 0;
+    MG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(GEMM_EUNSUPPORTED, "device %d: at most %d devices", dev,
+                                                          kMaxScratchDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(GEMM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GEMM_OK;
+}
+
 }  // namespace mg
 
 using namespace mg;
@@ -393,6 +427,34 @@ int gemm_plain_workspace_bytes(const gemm_problem_t *p, uint64_t *bytes_out) {
     tuner_choose(p->mode, p->m, p->n, p->k, &cfg, &split);
     *bytes_out = (uint64_t)plain_ws_bytes(*p, cfg, split);
     return GEMM_OK;
+}
+
+// Allocation-free plain product: gemm_plain's plan, with its workspace in a
+// fixed device array instead of the per-stream library workspace.
+int gemm_plain_noalloc(const gemm_problem_t *p, void *stream) {
+    clear_error();
+    int rc = validate(p);
+    if (rc != GEMM_OK) return rc;
+    if (p->m == 0 || p->n == 0) return GEMM_OK;
+    int cfg = 0, split = 1;
+    void *ws = nullptr;
+    if (p->k > 0) {
+        int count = 0;
+        configs(p->mode, &count);
+        if (count == 0) return fail(GEMM_EUNSUPPORTED, "mode %d has no kernels", p->mode);
+        tuner_choose(p->mode, p->m, p->n, p->k, &cfg, &split);
+        const int64_t need = plain_ws_bytes(*p, cfg, split);
+        if (need > GEMM_NOALLOC_SCRATCH_BYTES)
+            return fail(GEMM_EINVAL,
+                        "this product needs %lld bytes of workspace; gemm_plain_noalloc holds at most %lld "
+                        "(use gemm_plain)",
+                        (long long)need, (long long)GEMM_NOALLOC_SCRATCH_BYTES);
+        if (need > 0) {
+            rc = noalloc_scratch(&ws);
+            if (rc != GEMM_OK) return rc;
+        }
+    }
+    return enqueue_plain(*p, cfg, split, ws, (hipStream_t)stream);
 }
 
 int gemm_convert_f32(const float *x, int64_t count, int32_t to_mode, void *out, void *stream) {

@@ -93,4 +93,8 @@ std::unique_lock<std::mutex> lock_stream_workspaces(hipStream_t s);
 
 uint64_t now_ns();
 
+// Address of the allocation-free entry point's device scratch on the current
+// device (looked up once per device).
+int noalloc_scratch(void **out);
+
 }  // namespace mg
