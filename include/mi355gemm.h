@@ -262,6 +262,16 @@ int gemm_grouped_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t o
  * enqueues nothing. */
 int gemm_grouped_plan(const gemm_problem_t *ps, int32_t count, int32_t *cfg_out);
 
+/* The static schedule gemm_grouped builds for this list (validates like
+ * gemm_grouped; host only, no device call): *nwg_out workgroups (workgroup w
+ * runs on XCD w mod 8) and *ntiles_out output tiles; when the arrays are not
+ * NULL, wg_first[0..nwg] (workgroup w runs tiles wg_first[w] ..
+ * wg_first[w+1]-1, in order) and, per tile, the index of its problem in
+ * `ps` and its first output row and column.  Call once with NULL arrays
+ * for the sizes. */
+int gemm_grouped_schedule(const gemm_problem_t *ps, int32_t count, int32_t *nwg_out, int32_t *ntiles_out,
+                          int32_t *wg_first, int32_t *tile_problem, int32_t *tile_m0, int32_t *tile_n0);
+
 /* Build a graph that replays the grouped launch for this problem list
  * (descriptors are uploaded once, into graph-owned device memory).  The
  * problems' pointers must stay valid for the graph's lifetime. */

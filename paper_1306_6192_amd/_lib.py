@@ -101,6 +101,8 @@ _SIGS = {
     "gemm_grouped_info": (c_int32, [c_int32, POINTER(c_int32)]),
     "gemm_grouped_lookup": (c_int32, [c_int32, c_int64, c_int64, c_int64, POINTER(c_int32)]),
     "gemm_grouped_plan": (c_int32, [_P, c_int32, POINTER(c_int32)]),
+    "gemm_grouped_schedule": (c_int32, [_P, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                                        POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
     "gemm_graph_launch": (c_int32, [c_void_p, c_void_p]),
     "gemm_graph_destroy": (c_int32, [c_void_p]),
     "gemm_tune": (c_int32, [c_int32, c_int64, c_int64, c_int64, c_void_p]),

@@ -31,6 +31,6 @@ const KernelCfg *lp_configs_bf16(int *count) {
 }
 
 static const GroupedKernel kGrouped =
-    make_grouped<LpCfg<GEMM_MODE_BF16, 128, 128, 32>, LpCfg<GEMM_MODE_BF16, 64, 64>, 3>(13, 6);
+    make_grouped<LpCfg<GEMM_MODE_BF16, 128, 128, 32>, LpCfg<GEMM_MODE_BF16, 64, 64>, GROUPED_OCC, GROUPED_DEPTH>(13, 6);
 
 const GroupedKernel *lp_grouped_bf16() { return &kGrouped; }

@@ -14,6 +14,9 @@ static const KernelCfg kTable[] = {
     make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 256, 256, 4>, 1, 16>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 256, 128, 4>, 1, 16>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 128, 256, 4>, 1, 16>(), make_cfg<Lp2Cfg<GEMM_MODE_F8E4M3, 128, 128, 4>, 2, 16>(),
+    // register-staged 128 x 128 with k-tiles of 64 (half the LDS): the
+    // grouped launch's large tile (16 KB of operands per k-tile)
+    make_cfg<LpCfg<GEMM_MODE_F8E4M3, 128, 128, 64>, 3>(),
 };
 
 const KernelCfg *lp_configs_f8(int *count) {
@@ -22,6 +25,6 @@ const KernelCfg *lp_configs_f8(int *count) {
 }
 
 static const GroupedKernel kGrouped =
-    make_grouped<LpCfg<GEMM_MODE_F8E4M3, 128, 128>, LpCfg<GEMM_MODE_F8E4M3, 64, 64>, 2>(3, 6);
+    make_grouped<LpCfg<GEMM_MODE_F8E4M3, 128, 128, 64>, LpCfg<GEMM_MODE_F8E4M3, 64, 64>, GROUPED_OCC, GROUPED_DEPTH>(11, 6);
 
 const GroupedKernel *lp_grouped_f8() { return &kGrouped; }

@@ -15,12 +15,14 @@ static const KernelCfg kTable[] = {
 
 const KernelCfg *lp_configs_bf16(int *count);
 
-// The register-staged tiles above (any shape; the grouped launch uses two of
-// them), then one pre-split entry per asynchronous-copy BF16 tile with
+// The register-staged tiles above (any shape), then one pre-split entry per
+// asynchronous-copy BF16 tile with
 // k-tiles of 32: those run the split form as a BF16 product over interleaved
 // operand copies and give the same bits (the BF16 kernels themselves live in
 // the BF16 table).  A 32-k split-K grain of the split form is three such
 // k-tiles of the interleaved product; a k-tile of 64 would straddle grains.
+// Last, the register-staged 128 x 128 tile with k-tiles of 16 (the grouped
+// launch's large tile).
 const KernelCfg *lp_configs_split(int *count) {
     static const std::vector<KernelCfg> table = [] {
         std::vector<KernelCfg> t(std::begin(kTable), std::end(kTable));
@@ -33,15 +35,23 @@ const KernelCfg *lp_configs_split(int *count) {
                 k.presplit = 1;
                 t.push_back(k);
             }
+        t.push_back(make_cfg<LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 128, 128, 16>, 3>());
         return t;
     }();
     *count = (int)table.size();
     return table.data();
 }
 
-// two workgroups' launch bound, but the 128 x 128 tile's two-plane ring
-// leaves room in LDS for one
-static const GroupedKernel kGrouped =
-    make_grouped<LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 128, 128>, LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 64, 64>, 2>(2, 5);
-
-const GroupedKernel *lp_grouped_split() { return &kGrouped; }
+// The grouped launch's tiles: 128 x 128 with k-tiles of 16 (the last entry
+// of the table above) and 64 x 64, 16 KB of operands per k-tile each.
+const GroupedKernel *lp_grouped_split() {
+    static const GroupedKernel k = [] {
+        GroupedKernel g = make_grouped<LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 128, 128, 16>,
+                                       LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 64, 64>, GROUPED_OCC, GROUPED_DEPTH>(0, 5);
+        int n = 0;
+        lp_configs_split(&n);
+        g.cfg_idx[0] = n - 1;
+        return g;
+    }();
+    return &k;
+}

@@ -7,6 +7,8 @@
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <queue>
+#include <vector>
 
 #include "grouped.hpp"
 
@@ -57,12 +59,135 @@ const GroupedKernel *grouped_kernel(int mode) {
     return lp_grouped(mode);
 }
 
+// Cost of one output tile in the static schedule, in microseconds of one
+// workgroup: its k-tiles, each bounded by the operand bytes it moves (16 KB
+// at the workgroup's share of HBM bandwidth) or by its MFMA work at the
+// mode's rate (whichever is longer), plus the accumulator store and the
+// per-tile overhead.
+static double tile_cost_us(int mode, const KernelCfg &kc, int64_t k, int wg_per_cu) {
+    const double cus = (double)num_cus();
+    const double slots = cus * std::max(1, wg_per_cu);
+    const double bw = 8.0e6 / slots;                    // bytes per microsecond per workgroup
+    double peak;                                        // flop per microsecond per workgroup
+    switch (mode) {
+        case GEMM_MODE_F32: peak = 157.3e6; break;
+        case GEMM_MODE_F8E4M3: peak = 5000.0e6; break;
+        case GEMM_MODE_F32_SPLIT_BF16X3: peak = 2500.0e6 / 3.0; break;
+        default: peak = 2500.0e6; break;
+    }
+    peak /= slots;
+    const int64_t nkt = std::max<int64_t>(1, (k + kc.bk - 1) / kc.bk);
+    const double es = (double)elem_size(mode);
+    const double kt_bytes = (double)(kc.bm + kc.bn) * kc.bk * es;
+    const double kt_flops = 2.0 * kc.bm * kc.bn * kc.bk;
+    const double per_kt = std::max(kt_bytes / bw, kt_flops / peak);
+    return (double)nkt * per_kt + (double)kc.bm * kc.bn * 4.0 / bw + 1.0;
+}
+
+// Static schedule of the grouped launch.  Workgroup w runs on XCD w % 8 (the
+// dispatcher deals workgroups out round-robin), and each XCD has an L2 of its
+// own, so the tiles of a problem are kept on one XCD where the balance
+// allows: problems are placed whole, costliest first, on the least-loaded
+// XCD, except those costing more than a quarter of an XCD's fair share,
+// whose tiles are placed one by one.  Within an XCD, tiles are dealt
+// costliest first over its workgroups in snake order.  The schedule depends
+// on the problem list only.
+// Tile t of problem p (in the grouped row order of the plain launch: groups
+// of 8 tile rows, column by column within a group).
+static GroupTile tile_entry(const GroupPlan &plan, const KernelCfg *t, int p, int tile) {
+    const GroupDesc &d = plan.descs[p];
+    const KernelCfg &kc = t[plan.gk->cfg_idx[d.cfg]];
+    const int group_m = 8;
+    const int per_group = group_m * d.P.tiles_n;
+    const int g = tile / per_group;
+    const int first_m = g * group_m;
+    const int gsz = std::min(d.P.tiles_m - first_m, group_m);
+    const int in = tile - g * per_group;
+    GroupTile e;
+    e.p = p;
+    e.m0 = (first_m + in % gsz) * kc.bm;
+    e.n0 = (in / gsz) * kc.bn;
+    e.nkt = std::max(1, (d.P.k + kc.bk - 1) / kc.bk);
+    return e;
+}
+
+static void build_schedule(GroupPlan &plan, const std::vector<double> &prob_cost,
+                           const std::vector<int> &prob_tiles) {
+    int tcount = 0;
+    const KernelCfg *tab = configs(plan.mode, &tcount);
+    const int np = (int)plan.descs.size();
+    const int nwg = plan.nwg;
+    const int nx = std::min(GEMM_NUM_XCD, nwg);
+    typedef std::pair<double, int> L;   // (load per resident workgroup, index)
+    // XCD x hosts workgroups x, x + 8, ... below nwg
+    std::vector<double> xcap(nx, 0.0);
+    for (int w = 0; w < nwg; ++w) xcap[w % GEMM_NUM_XCD] += 1.0;
+    std::priority_queue<L, std::vector<L>, std::greater<L>> xheap;
+    for (int x = 0; x < nx; ++x) xheap.push({0.0, x});
+    double total = 0.0;
+    for (int p = 0; p < np; ++p) total += prob_cost[p] * prob_tiles[p];
+    std::vector<int> order(np);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return prob_cost[a] * prob_tiles[a] > prob_cost[b] * prob_tiles[b];
+    });
+    // tiles grouped by XCD: (problem, tile) in placement order
+    std::vector<std::vector<std::pair<int, int>>> xt(nx);
+    const double split_above = 0.25 * total / nx;
+    auto place = [&](int p, int t0, int t1, double c) {
+        L top = xheap.top();
+        xheap.pop();
+        for (int t = t0; t < t1; ++t) xt[top.second].push_back({p, t});
+        top.first += c * (t1 - t0) / xcap[top.second];
+        xheap.push(top);
+    };
+    for (int p : order) {
+        const int nt = prob_tiles[p];
+        if (prob_cost[p] * nt > split_above)
+            for (int t = 0; t < nt; ++t) place(p, t, t + 1, prob_cost[p]);
+        else
+            place(p, 0, nt, prob_cost[p]);
+    }
+    // within an XCD: costliest first, dealt over the XCD's workgroups in
+    // snake order (w0 .. wn, wn .. w0, ...), which balances runs of equal
+    // costs like the longest-processing-time rule at linear cost
+    std::vector<int> wg_of;
+    std::vector<std::pair<int, int>> flat;
+    flat.reserve(plan.total_tiles);
+    wg_of.reserve(plan.total_tiles);
+    std::vector<int32_t> count(nwg, 0);
+    for (int x = 0; x < nx; ++x) {
+        auto &v = xt[x];
+        std::stable_sort(v.begin(), v.end(), [&](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+            return prob_cost[a.first] > prob_cost[b.first];
+        });
+        const int nw = (nwg - x + GEMM_NUM_XCD - 1) / GEMM_NUM_XCD;   // workgroups x, x + 8, ...
+        for (size_t i = 0; i < v.size(); ++i) {
+            const int round = (int)(i / nw), j = (int)(i % nw);
+            const int w = x + GEMM_NUM_XCD * ((round & 1) ? nw - 1 - j : j);
+            flat.push_back(v[i]);
+            wg_of.push_back(w);
+            ++count[w];
+        }
+    }
+    // counting sort by workgroup (placement order kept within a workgroup)
+    plan.wg_first.assign(nwg + 1, 0);
+    for (int w = 0; w < nwg; ++w) plan.wg_first[w + 1] = plan.wg_first[w] + count[w];
+    std::vector<int32_t> pos(plan.wg_first.begin(), plan.wg_first.end() - 1);
+    plan.tiles.resize(flat.size());
+    for (size_t i = 0; i < flat.size(); ++i)
+        plan.tiles[pos[wg_of[i]]++] = tile_entry(plan, tab, flat[i].first, flat[i].second);
+}
+
 int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan, int force) {
     if (count < 0) return fail(GEMM_EINVAL, "negative problem count");
     if (count > 0 && !ps) return fail(GEMM_EINVAL, "problem array is NULL");
     plan.descs.clear();
     plan.src.clear();
+    plan.tiles.clear();
+    plan.wg_first.clear();
     plan.total_tiles = 0;
+    plan.nwg = 0;
     plan.mode = count > 0 ? ps[0].mode : GEMM_MODE_F32;
     for (int i = 0; i < count; ++i) {
         int rc = validate(&ps[i]);
@@ -77,12 +202,6 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan, i
     if (!plan.gk) return fail(GEMM_EUNSUPPORTED, "mode %d has no grouped kernel", plan.mode);
     int tcount = 0;
     const KernelCfg *t = configs(plan.mode, &tcount);
-    struct Item {
-        GroupDesc d;
-        double cost;
-        int tiles;
-        int src;
-    };
     // A launch whose chosen tiles would not fill every resident-workgroup
     // slot runs every problem on the smaller tile instead (the tile does not
     // change the bits): a handful of mid-size problems then spread over the
@@ -92,92 +211,80 @@ int build_group_plan(const gemm_problem_t *ps, int32_t count, GroupPlan &plan, i
                           ? 1
                           : 0;
     int64_t chosen_tiles = 0;
+    std::vector<int8_t> choice(count, 0);
     for (int i = 0; i < count; ++i) {
         const gemm_problem_t &p = ps[i];
         if (p.m == 0 || p.n == 0) continue;
-        const KernelCfg &kc = t[plan.gk->cfg_idx[force >= 0 ? force : grouped_choose(p.mode, p.m, p.n, p.k)]];
+        choice[i] = (int8_t)(force >= 0 ? force : grouped_choose(p.mode, p.m, p.n, p.k));
+        const KernelCfg &kc = t[plan.gk->cfg_idx[choice[i]]];
         chosen_tiles += ((p.m + kc.bm - 1) / kc.bm) * ((p.n + kc.bn - 1) / kc.bn);
     }
-    const bool underfilled = force < 0 && chosen_tiles < (int64_t)num_cus() * plan.gk->wg_per_cu;
-    std::vector<Item> items;
-    items.reserve(count);
+    const int64_t slots = (int64_t)num_cus() * plan.gk->wg_per_cu;
+    const bool underfilled = force < 0 && chosen_tiles < slots;
+    std::vector<double> cost;
+    std::vector<int> ntiles;
+    cost.reserve(count);
+    ntiles.reserve(count);
+    plan.descs.reserve(count);
+    plan.src.reserve(count);
+    int64_t total = 0;
     for (int i = 0; i < count; ++i) {
         const gemm_problem_t &p = ps[i];
         if (p.m == 0 || p.n == 0) continue;
-        Item it;
-        memset(&it.d, 0, sizeof(it.d));
-        it.src = i;
-        it.d.cfg = force >= 0 ? force : underfilled ? small : grouped_choose(p.mode, p.m, p.n, p.k);
-        const KernelCfg &kc = t[plan.gk->cfg_idx[it.d.cfg]];
-        it.d.P = make_launch(p, kc, 1).P;
-        it.tiles = it.d.P.tiles_m * it.d.P.tiles_n;
-        it.cost = (double)kc.bm * kc.bn * (double)std::max<int64_t>(p.k, 1);
-        items.push_back(it);
+        GroupDesc d;
+        memset(&d, 0, sizeof(d));
+        d.cfg = underfilled ? small : choice[i];
+        const KernelCfg &kc = t[plan.gk->cfg_idx[d.cfg]];
+        d.P = make_launch(p, kc, 1).P;
+        const int64_t nt = (int64_t)d.P.tiles_m * d.P.tiles_n;
+        total += nt;
+        if (total > INT32_MAX) return fail(GEMM_EUNSUPPORTED, "grouped launch above 2^31 tiles");
+        plan.descs.push_back(d);
+        plan.src.push_back(i);
+        cost.push_back(tile_cost_us(plan.mode, kc, p.k, plan.gk->wg_per_cu));
+        ntiles.push_back((int)nt);
     }
-    // Longest tiles first: workgroups take tiles from a queue in this order,
-    // so the costliest tiles start first and the cheap ones fill the tail.
-    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
-    int64_t start = 0;
-    for (auto &it : items) {
-        it.d.tile_start = (int32_t)start;
-        start += it.tiles;
-        if (start > INT32_MAX) return fail(GEMM_EUNSUPPORTED, "grouped launch above 2^31 tiles");
-        plan.descs.push_back(it.d);
-        plan.src.push_back(it.src);
-    }
-    plan.total_tiles = (int)start;
-    plan.nwg = (int)std::min<int64_t>(start, (int64_t)num_cus() * plan.gk->wg_per_cu);
+    plan.total_tiles = (int)total;
+    plan.nwg = (int)std::min<int64_t>(total, slots);
+    if (total > 0) build_schedule(plan, cost, ntiles);
     return GEMM_OK;
 }
 
-int enqueue_group(const GroupPlan &plan, const GroupDesc *dev_descs, int32_t *counters, hipStream_t s) {
+// The plan's device image: descriptors, then the workgroups' list offsets,
+// then the tile lists, each part 256-byte aligned.
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t plan_image_bytes(const GroupPlan &plan) {
+    return align256(plan.descs.size() * sizeof(GroupDesc)) + align256(plan.wg_first.size() * sizeof(int32_t)) +
+           align256(plan.tiles.size() * sizeof(GroupTile));
+}
+
+void plan_image_write(const GroupPlan &plan, void *dst) {
+    uint8_t *d = static_cast<uint8_t *>(dst);
+    memcpy(d, plan.descs.data(), plan.descs.size() * sizeof(GroupDesc));
+    d += align256(plan.descs.size() * sizeof(GroupDesc));
+    memcpy(d, plan.wg_first.data(), plan.wg_first.size() * sizeof(int32_t));
+    d += align256(plan.wg_first.size() * sizeof(int32_t));
+    memcpy(d, plan.tiles.data(), plan.tiles.size() * sizeof(GroupTile));
+}
+
+int enqueue_group(const GroupPlan &plan, const void *dev_image, hipStream_t s) {
     if (plan.total_tiles == 0) return GEMM_OK;
+    const uint8_t *d = static_cast<const uint8_t *>(dev_image);
     GroupedArgs G;
-    G.descs = dev_descs;
-    G.count = (int32_t)plan.descs.size();
-    G.total_tiles = plan.total_tiles;
-    G.counters = counters;
+    G.descs = reinterpret_cast<const GroupDesc *>(d);
+    d += align256(plan.descs.size() * sizeof(GroupDesc));
+    G.wg_first = reinterpret_cast<const int32_t *>(d);
+    d += align256(plan.wg_first.size() * sizeof(int32_t));
+    G.tiles = reinterpret_cast<const GroupTile *>(d);
     MG_HIP(plan.gk->launch(G, plan.nwg, s));
     return GEMM_OK;
 }
 
-int alloc_counters(int32_t **out) {
-    *out = nullptr;
-    void *p = nullptr;
-    if (hipMalloc(&p, 256) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(GEMM_ENOMEM, "work-queue counters");
-    }
-    if (hipMemset(p, 0, 256) != hipSuccess) {
-        (void)hipFree(p);
-        return fail(GEMM_EHIP, "zeroing work-queue counters failed");
-    }
-    *out = static_cast<int32_t *>(p);
-    return GEMM_OK;
-}
-
-// The work-queue counters of a stream's grouped launches (zeroed once; every
-// launch leaves them at zero).
-static std::mutex g_cnt_mu;
-static std::map<std::pair<int, hipStream_t>, int32_t *> g_cnt;
-
-static int stream_counters(hipStream_t s, int32_t **out) {
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    std::lock_guard<std::mutex> lk(g_cnt_mu);
-    int32_t *&c = g_cnt[{dev, s}];
-    if (!c) {
-        int rc = alloc_counters(&c);
-        if (rc != GEMM_OK) return rc;
-    }
-    *out = c;
-    return GEMM_OK;
-}
-
-// Pinned host staging of the descriptor upload: a ring of buffers per
-// (device, stream), so that the host only waits for the copy issued
-// kRing calls earlier and can run ahead of the device by that many calls.
-// Callers on one stream take the stage's lock for the whole upload.
+// Pinned host staging of the plan upload: a ring of buffers per (device,
+// stream), so that the host only waits for the copy issued kRing calls
+// earlier and can run ahead of the device by that many calls.  Callers on
+// one stream take the stage's lock for the whole upload.
 static const int kRing = 4;
 struct HostStage {
     std::mutex mu;
@@ -189,8 +296,8 @@ struct HostStage {
 static std::mutex g_stage_mu;
 static std::map<std::pair<int, hipStream_t>, HostStage *> g_stage;
 
-int upload_descs(const GroupPlan &plan, hipStream_t s, const GroupDesc **dev_out) {
-    const size_t bytes = plan.descs.size() * sizeof(GroupDesc);
+int upload_plan(const GroupPlan &plan, hipStream_t s, const void **dev_out) {
+    const size_t bytes = plan_image_bytes(plan);
     DevBuf *db = stream_workspace(s, 1);
     int rc = db->ensure(std::max<size_t>(bytes, 256), s);
     if (rc != GEMM_OK) return rc;
@@ -215,10 +322,10 @@ int upload_descs(const GroupPlan &plan, hipStream_t s, const GroupDesc **dev_out
         MG_HIP(hipHostMalloc(&st->host[b], std::max<size_t>(bytes, 4096), hipHostMallocDefault));
         st->bytes[b] = std::max<size_t>(bytes, 4096);
     }
-    memcpy(st->host[b], plan.descs.data(), bytes);
+    plan_image_write(plan, st->host[b]);
     MG_HIP(hipMemcpyAsync(db->ptr, st->host[b], bytes, hipMemcpyHostToDevice, s));
     MG_HIP(hipEventRecord(st->ev[b], s));
-    *dev_out = static_cast<const GroupDesc *>(db->ptr);
+    *dev_out = db->ptr;
     return GEMM_OK;
 }
 
@@ -254,8 +361,7 @@ static int time_median(hipStream_t s, int reps, F run, float *ms_out) {
 struct GroupGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    void *descs = nullptr;
-    int32_t *counters = nullptr;
+    void *image = nullptr;   // the plan's device image (graph-owned)
 };
 
 }  // namespace mg
@@ -270,14 +376,11 @@ int gemm_grouped(const gemm_problem_t *ps, int32_t count, void *stream) {
     int rc = build_group_plan(ps, count, plan);
     if (rc != GEMM_OK || plan.total_tiles == 0) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const GroupDesc *dd = nullptr;
-    int32_t *cnt = nullptr;
-    rc = stream_counters(s, &cnt);
-    if (rc != GEMM_OK) return rc;
+    const void *img = nullptr;
     std::unique_lock<std::mutex> ws_lock = lock_stream_workspaces(s);
-    rc = upload_descs(plan, s, &dd);
+    rc = upload_plan(plan, s, &img);
     if (rc != GEMM_OK) return rc;
-    return enqueue_group(plan, dd, cnt, s);
+    return enqueue_group(plan, img, s);
 }
 
 int gemm_grouped_graph_create(const gemm_problem_t *ps, int32_t count, void **graph_out) {
@@ -289,19 +392,16 @@ int gemm_grouped_graph_create(const gemm_problem_t *ps, int32_t count, void **gr
     if (rc != GEMM_OK) return rc;
     GroupGraph *g = new GroupGraph();
     if (plan.total_tiles > 0) {
-        const size_t bytes = plan.descs.size() * sizeof(GroupDesc);
+        const size_t bytes = plan_image_bytes(plan);
+        std::vector<uint8_t> host(bytes);
+        plan_image_write(plan, host.data());
         hipStream_t cs = nullptr;
-        rc = alloc_counters(&g->counters);
-        if (rc != GEMM_OK) {
-            delete g;
-            return rc;
-        }
-        hipError_t e = hipMalloc(&g->descs, bytes);
-        if (e == hipSuccess) e = hipMemcpy(g->descs, plan.descs.data(), bytes, hipMemcpyHostToDevice);
+        hipError_t e = hipMalloc(&g->image, bytes);
+        if (e == hipSuccess) e = hipMemcpy(g->image, host.data(), bytes, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            rc = enqueue_group(plan, static_cast<const GroupDesc *>(g->descs), g->counters, cs);
+            rc = enqueue_group(plan, g->image, cs);
             hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
             if (rc == GEMM_OK && e2 != hipSuccess) e = e2;
         }
@@ -310,8 +410,7 @@ int gemm_grouped_graph_create(const gemm_problem_t *ps, int32_t count, void **gr
         if (e != hipSuccess || rc != GEMM_OK) {
             if (g->exec) (void)hipGraphExecDestroy(g->exec);
             if (g->graph) (void)hipGraphDestroy(g->graph);
-            if (g->descs) (void)hipFree(g->descs);
-            if (g->counters) (void)hipFree(g->counters);
+            if (g->image) (void)hipFree(g->image);
             delete g;
             if (rc != GEMM_OK) return rc;
             return fail(GEMM_EHIP, "graph capture failed: %s", hipGetErrorString(e));
@@ -347,8 +446,7 @@ int gemm_tune_grouped(int32_t mode, int64_t m, int64_t n, int64_t k, void *strea
     const int64_t per = abytes + bbytes + cbytes;
     while (count > 1 && count * per > ((int64_t)1 << 30)) count = (count + 1) / 2;
     uint8_t *buf = nullptr;
-    void *descs = nullptr;
-    int32_t *counters = nullptr;
+    void *image = nullptr;
     if (hipMalloc(&buf, (size_t)(count * per)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GEMM_ENOMEM, "grouped tuning buffers do not fit");
@@ -374,29 +472,29 @@ int gemm_tune_grouped(int32_t mode, int64_t m, int64_t n, int64_t k, void *strea
     // non-zero operands: the clock under load depends on the data
     if (launch_fill_tuning(buf, count * per / es, (int)es, 3u, s) != hipSuccess)
         rc = fail(GEMM_EHIP, "filling the tuning operands failed");
-    if (rc == GEMM_OK) rc = alloc_counters(&counters);
     float batch_ms[2] = {0.f, 0.f}, alone_ms[2] = {0.f, 0.f};
     for (int o = 0; o < 2 && rc == GEMM_OK; ++o) {
         GroupPlan plan;
         rc = build_group_plan(ps.data(), (int32_t)count, plan, o);
         if (rc != GEMM_OK) break;
-        const size_t bytes = plan.descs.size() * sizeof(GroupDesc);
-        if (descs) (void)hipFree(descs);
-        descs = nullptr;
-        if (hipMalloc(&descs, bytes) != hipSuccess ||
-            hipMemcpy(descs, plan.descs.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        const size_t bytes = plan_image_bytes(plan);
+        std::vector<uint8_t> host(bytes);
+        plan_image_write(plan, host.data());
+        if (image) (void)hipFree(image);
+        image = nullptr;
+        if (hipMalloc(&image, bytes) != hipSuccess ||
+            hipMemcpy(image, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
             (void)hipGetLastError();
             rc = fail(GEMM_EHIP, "grouped tuning descriptors");
             break;
         }
-        rc = time_median(s, 7, [&] { return enqueue_group(plan, static_cast<const GroupDesc *>(descs), counters, s); },
+        rc = time_median(s, 7, [&] { return enqueue_group(plan, image, s); },
                          &batch_ms[o]);
         if (rc != GEMM_OK) break;
         rc = time_median(s, 7, [&] { return enqueue_plain(ps[0], gk->cfg_idx[o], 1, nullptr, s); }, &alone_ms[o]);
     }
     if (rc == GEMM_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(GEMM_EHIP, "stream sync failed");
-    if (descs) (void)hipFree(descs);
-    if (counters) (void)hipFree(counters);
+    if (image) (void)hipFree(image);
     (void)hipFree(buf);
     if (rc != GEMM_OK) return rc;
     tuner_record_grouped(mode, m, n, k, batch_ms[1] < batch_ms[0] ? 1 : 0, alone_ms[1] < alone_ms[0] ? 1 : 0);
@@ -442,6 +540,26 @@ int gemm_grouped_plan(const gemm_problem_t *ps, int32_t count, int32_t *cfg_out)
     return GEMM_OK;
 }
 
+int gemm_grouped_schedule(const gemm_problem_t *ps, int32_t count, int32_t *nwg_out, int32_t *ntiles_out,
+                          int32_t *wg_first, int32_t *tile_problem, int32_t *tile_m0, int32_t *tile_n0) {
+    clear_error();
+    if (!nwg_out || !ntiles_out) return fail(GEMM_EINVAL, "nwg_out or ntiles_out is NULL");
+    GroupPlan plan;
+    int rc = build_group_plan(ps, count, plan);
+    if (rc != GEMM_OK) return rc;
+    *nwg_out = plan.nwg;
+    *ntiles_out = plan.total_tiles;
+    if (wg_first)
+        for (int w = 0; w <= plan.nwg && plan.nwg > 0; ++w) wg_first[w] = plan.wg_first[w];
+    for (int i = 0; i < plan.total_tiles; ++i) {
+        const GroupTile &e = plan.tiles[i];
+        if (tile_problem) tile_problem[i] = plan.src[e.p];
+        if (tile_m0) tile_m0[i] = e.m0;
+        if (tile_n0) tile_n0[i] = e.n0;
+    }
+    return GEMM_OK;
+}
+
 int gemm_graph_launch(void *graph, void *stream) {
     clear_error();
     if (!graph) return fail(GEMM_EINVAL, "graph is NULL");
@@ -461,8 +579,7 @@ int gemm_graph_destroy(void *graph) {
         (void)hipGraphExecDestroy(g->exec);
     }
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    if (g->descs) (void)hipFree(g->descs);
-    if (g->counters) (void)hipFree(g->counters);
+    if (g->image) (void)hipFree(g->image);
     delete g;
     return GEMM_OK;
 }

@@ -6,19 +6,24 @@
 // Descriptor of one problem inside a grouped (persistent) launch.
 struct GroupDesc {
     TileProblem P;        // splits == 1
-    int32_t tile_start;   // first global tile index of this problem
     int32_t cfg;          // 0 or 1: which of the grouped kernel's two tile configurations
-    int32_t pad[2];
+    int32_t pad[3];
 };
 
+// One entry of a workgroup's tile list: descriptor index, the tile's first
+// output row and column, and its number of k-tiles (at least 1).
+struct GroupTile {
+    int32_t p;
+    int32_t m0, n0;
+    int32_t nkt;
+};
+
+// A grouped launch: workgroup w computes tiles[wg_first[w] .. wg_first[w+1])
+// in that order (the static schedule the host builds).
 struct GroupedArgs {
     const GroupDesc *descs;
-    int32_t count;
-    int32_t total_tiles;
-    // Work queue: counters[0] = next tile to hand out, counters[1] = workgroups
-    // finished.  Both start at zero; the last workgroup to finish puts them
-    // back to zero, so a replay (or the next launch) finds them ready.
-    int32_t *counters;
+    const GroupTile *tiles;
+    const int32_t *wg_first;
 };
 
 typedef hipError_t (*PlainLaunchFn)(const TileProblem &P, int nwg, hipStream_t s);

@@ -52,7 +52,6 @@ struct Slot {
     void *host = nullptr;
     size_t host_bytes = 0;
     DevBuf ws;                           // split-K workspace (plain executor)
-    int32_t *counters = nullptr;         // grouped-launch work queue
     std::vector<Request *> running;      // empty = idle
     uint64_t fake_done_at = 0;
     bool fake_fail = false;
@@ -118,8 +117,6 @@ int Server::init() {
         for (Slot &s : slots) {
             MG_HIP(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
             MG_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
-            int rc = alloc_counters(&s.counters);
-            if (rc != GEMM_OK) return rc;
         }
     }
     thread = std::thread([this] { loop(); });
@@ -234,7 +231,7 @@ int Server::launch_batch(Slot &s, std::vector<Request *> &b) {
     int rc = build_group_plan(ps.data(), (int)ps.size(), plan);
     if (rc != GEMM_OK) return rc;
     if (plan.total_tiles > 0) {
-        const size_t bytes = plan.descs.size() * sizeof(GroupDesc);
+        const size_t bytes = plan_image_bytes(plan);
         rc = s.descs.ensure(std::max<size_t>(bytes, 4096), s.stream);
         if (rc != GEMM_OK) return rc;
         if (s.host_bytes < bytes) {
@@ -245,9 +242,9 @@ int Server::launch_batch(Slot &s, std::vector<Request *> &b) {
             s.host_bytes = std::max<size_t>(bytes, 65536);
         }
         // the slot is idle: its previous upload has completed
-        memcpy(s.host, plan.descs.data(), bytes);
+        plan_image_write(plan, s.host);
         MG_HIP(hipMemcpyAsync(s.descs.ptr, s.host, bytes, hipMemcpyHostToDevice, s.stream));
-        rc = enqueue_group(plan, static_cast<const GroupDesc *>(s.descs.ptr), s.counters, s.stream);
+        rc = enqueue_group(plan, s.descs.ptr, s.stream);
         if (rc != GEMM_OK) return rc;
     }
     MG_HIP(hipEventRecord(s.done, s.stream));
@@ -448,7 +445,6 @@ int gemm_serve_destroy(void *server) {
         if (sl.host) (void)hipHostFree(sl.host);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        if (sl.counters) (void)hipFree(sl.counters);
     }
     for (auto &kv : s->by_ticket) delete kv.second;
     delete s;

@@ -1,0 +1,491 @@
+// Grouped persistent launch with a streamed operand pipeline.
+//
+// Many independent products (any shapes, any strides and alignments) in one
+// launch.  The host lays every output tile of every problem out on a static
+// schedule (an ordered tile list per workgroup, see grouped.cpp); each
+// workgroup walks its list as one stream of k-tiles and keeps the next
+// DEPTH-1 k-tiles of that stream in flight in a ring of register sets while
+// it multiplies the current one, across tile boundaries: the first k-tiles of
+// the next output tile are already loading while the current tile finishes,
+// so no tile pays the full HBM latency of its first k-tile.
+//
+// Per k-tile of the stream (one step):
+//   1. issue the 16-byte global loads of the k-tile DEPTH-1 steps ahead into
+//      its register set (always the same number of loads per k-tile, so that
+//      one vmcnt wait retires exactly the oldest set);
+//   2. multiply the current k-tile from LDS (the register-staged tiles' MFMA
+//      code, so the arithmetic and the bits are those of the plain launch of
+//      the same configuration);
+//   3. wait for the next k-tile's set, fix up its edge chunks (zero past k,
+//      realign the chunks read at clamped addresses) and write it to the
+//      other LDS stage (the register-staged tiles' LDS layout);
+//   4. after the last k-tile of an output tile, store its accumulators;
+//   5. one workgroup barrier.
+//
+// Loads never leave the operands: rows of A past m and columns of B past n
+// read clamped (valid) addresses whose results are never stored; k past the
+// end is zeroed after the load.  A 16-byte chunk that would run past the end
+// of a row is read from the row's other chunks' memory when another row
+// follows it in the matrix (rows are lda >= k apart, so the bytes exist),
+// and, in the matrix's last row only, read at the last whole chunk of the row
+// and shifted into place.  Problems whose k or n is below one chunk (16 bytes
+// of elements) take element-wise loads and a full wait instead.
+#pragma once
+
+#include "tile_f32.hpp"
+#include "tile_lp.hpp"
+
+// s_waitcnt vmcnt(N), the other counters left alone (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt_gs() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Register-staged tile configurations as the stream sees them: NA A-vectors
+// and NB B-vectors of 16 bytes per thread per k-tile, the tile-relative
+// position of each, and the LDS store / multiply / epilogue of the
+// configuration.
+template <class Cfg> struct GsOps;
+
+template <int BM, int BN, int WM, int WN, int BK>
+struct GsOps<F32Cfg<BM, BN, WM, WN, BK>> {
+    typedef F32Cfg<BM, BN, WM, WN, BK> Cfg;
+    static constexpr int ESZ = 4;
+    static constexpr int NA = Cfg::AV, NB = Cfg::BV;
+    typedef f32x16 Acc[Cfg::RB][Cfg::CB];
+    // A vector q: tile row r, k offset c; B vector q: k offset kr, tile column c
+    __device__ static __forceinline__ void a_pos(int q, int &r, int &c) {
+        const int idx = threadIdx.x + q * Cfg::THREADS;
+        r = idx / (BK / 4);
+        c = (idx % (BK / 4)) * 4;
+    }
+    __device__ static __forceinline__ void b_pos(int q, int &kr, int &c) {
+        const int idx = threadIdx.x + q * Cfg::THREADS;
+        kr = idx / (BN / 4);
+        c = (idx % (BN / 4)) * 4;
+    }
+    __device__ static __forceinline__ void store(uint8_t *stage, const u32x4 *v) {
+        f32x4 ra[NA], rb[NB];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) ra[q] = __builtin_bit_cast(f32x4, v[q]);
+#pragma unroll
+        for (int q = 0; q < NB; ++q) rb[q] = __builtin_bit_cast(f32x4, v[NA + q]);
+        f32_store_tiles<Cfg>(reinterpret_cast<float *>(stage), ra, rb);
+    }
+    __device__ static __forceinline__ void compute(const uint8_t *stage, Acc &acc) {
+        f32_compute_stage<Cfg>(reinterpret_cast<const float *>(stage), acc);
+    }
+};
+
+template <int MODE, int BM, int BN, int BK>
+struct GsOps<LpCfg<MODE, BM, BN, BK>> {
+    typedef LpCfg<MODE, BM, BN, BK> Cfg;
+    static constexpr int ESZ = Cfg::T::IN_ESZ;
+    static constexpr int NA = Cfg::AV, NB = Cfg::TKB;
+    typedef f32x16 Acc[Cfg::RB][Cfg::CB];
+    __device__ static __forceinline__ void a_pos(int q, int &r, int &c) {
+        const int idx = threadIdx.x + q * GEMM_THREADS;
+        r = idx / Cfg::VPR;
+        c = (idx % Cfg::VPR) * (16 / ESZ);
+    }
+    __device__ static __forceinline__ void b_pos(int q, int &kr, int &c) {
+        const int kb = threadIdx.x % Cfg::KBLK, nb = threadIdx.x / Cfg::KBLK;
+        kr = kb * Cfg::TKB + q;
+        c = nb * Cfg::VN;
+    }
+    __device__ static __forceinline__ void store(uint8_t *stage, const u32x4 *v) {
+        LpStage<Cfg> R;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) R.a[q] = v[q];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) R.b[q] = v[NA + q];
+        lp_store_tiles<Cfg>(stage, R);
+    }
+    __device__ static __forceinline__ void compute(const uint8_t *stage, Acc &acc) {
+        lp_compute_stage<Cfg>(stage, acc);
+    }
+};
+
+// The 16 bytes of v shifted down by `sb` bytes (0..15), zeros shifted in.
+__device__ __forceinline__ u32x4 gs_shift_down(const u32x4 &v, int sb) {
+    const int sw = sb >> 2, sr = sb & 3;
+    const uint32_t w0 = v[0], w1 = v[1], w2 = v[2], w3 = v[3];
+    auto pick = [&](int i) -> uint32_t {
+        return i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : i == 3 ? w3 : 0u;
+    };
+    u32x4 o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_alignbyte(pick(i + sw + 1), pick(i + sw), sr);
+    return o;
+}
+
+// Keep the first `nb` bytes of v (0..16), zero the rest.
+__device__ __forceinline__ u32x4 gs_keep_bytes(const u32x4 &v, int nb) {
+    u32x4 o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int left = nb - 4 * i;
+        const uint32_t m = left >= 4 ? 0xFFFFFFFFu : left <= 0 ? 0u : (0xFFFFFFFFu >> (32 - 8 * left));
+        o[i] = v[i] & m;
+    }
+    return o;
+}
+
+// Pointers read from the descriptors are kept as global-memory pointers, so
+// that accesses through them are global instructions, not flat ones (a flat
+// access also counts against the LDS counter, and every LDS wait would then
+// wait for the stream's loads too).
+typedef __attribute__((address_space(1))) const uint8_t gs_gu8;
+typedef __attribute__((address_space(1))) float gs_gf32;
+typedef u32x4 gs_u32x4_u __attribute__((aligned(1)));
+typedef __attribute__((address_space(1))) const gs_u32x4_u gs_gu32x4;
+
+// 16 bytes from any byte address of global memory (unaligned access is on).
+__device__ __forceinline__ u32x4 gs_ld16(gs_gu8 *p) { return *reinterpret_cast<gs_gu32x4 *>(p); }
+
+// 16 bytes of row r from element column c, zero outside [0, R) x [0, Cn),
+// element by element (the tiny problems' loads).
+template <int ESZ>
+__device__ __forceinline__ u32x4 gs_ld16_masked(gs_gu8 *base, int64_t ld, int r, int c, int R, int Cn) {
+    constexpr int N = 16 / ESZ;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if (r < R) {
+        gs_gu8 *p = base + ((int64_t)r * ld + c) * ESZ;
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+            if (c + e < Cn) {
+#pragma unroll
+                for (int i = 0; i < ESZ; ++i) {
+                    const int b = e * ESZ + i;
+                    w[b >> 2] |= (uint32_t)p[b] << (8 * (b & 3));
+                }
+            }
+    }
+    return (u32x4){w[0], w[1], w[2], w[3]};
+}
+
+// The accumulators of one tile to C (the element mapping of tile_epilogue:
+// lane l%32 of block cb holds output column CB*(l%32) + cb of the wave's
+// columns; register r of the 32x32 block holds row 8(r/4) + 4(l/32) + r%4).
+template <class Cfg>
+__device__ __forceinline__ void gs_epilogue(gs_gf32 *C, int64_t ldc, int M, int N, int m0, int n0, float scale,
+                                            const f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
+    const int l32 = lane & 31, g = lane >> 5;
+    const int col = n0 + wn * Cfg::TN + Cfg::CB * l32;
+    const bool full_cols = col + Cfg::CB <= N;
+#pragma unroll
+    for (int rb = 0; rb < Cfg::RB; ++rb) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = m0 + wm * Cfg::TM + rb * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+            if (row >= M) continue;
+            gs_gf32 *p = C + (int64_t)row * ldc + col;
+            if (full_cols) {
+#pragma unroll
+                for (int cb = 0; cb < Cfg::CB; ++cb) p[cb] = acc[rb][cb][r] * scale;
+            } else {
+#pragma unroll
+                for (int cb = 0; cb < Cfg::CB; ++cb)
+                    if (col + cb < N) p[cb] = acc[rb][cb][r] * scale;
+            }
+        }
+    }
+}
+
+// What the stream reads about one output tile: its schedule entry and its
+// problem's descriptor, through restrict-qualified pointers with a
+// wave-uniform index, so that the compiler keeps them in scalar registers
+// (scalar loads; no vector-memory wait).
+struct GsTile {
+    gs_gu8 *A, *B;
+    gs_gf32 *C;
+    int64_t lda, ldb, ldc;
+    int m, n, k;
+    float scale;
+    int cfg;        // 0 or 1
+    int m0, n0;
+    int nkt;        // k-tiles of the tile's configuration (at least 1)
+    bool tiny;      // k or n below one 16-byte chunk: element-wise loads
+};
+
+template <int ESZ>
+__device__ __forceinline__ GsTile gs_tile(const GroupDesc *__restrict__ descs, const GroupTile *__restrict__ tiles,
+                                          int i) {
+    const GroupTile e = tiles[__builtin_amdgcn_readfirstlane(i)];
+    const GroupDesc &d = descs[__builtin_amdgcn_readfirstlane(e.p)];
+    GsTile T;
+    T.A = (gs_gu8 *)d.P.A;
+    T.B = (gs_gu8 *)d.P.B;
+    T.C = (gs_gf32 *)d.P.C;
+    T.lda = d.P.lda;
+    T.ldb = d.P.ldb;
+    T.ldc = d.P.ldc;
+    T.m = d.P.m;
+    T.n = d.P.n;
+    T.k = d.P.k;
+    T.scale = d.P.scale;
+    T.cfg = d.cfg;
+    T.m0 = e.m0;
+    T.n0 = e.n0;
+    T.nkt = e.nkt;
+    T.tiny = T.k < 16 / ESZ || T.n < 16 / ESZ;
+    return T;
+}
+
+// Source addresses of the NV loads of k-tile kt of tile T for configuration
+// Cfg (see the file comment for the addresses).
+template <class Cfg, int NV>
+__device__ __forceinline__ void gs_addr_cfg(const GsTile &T, int kt, gs_gu8 *(&src)[NV]) {
+    typedef GsOps<Cfg> O;
+    static_assert(O::NA + O::NB == NV, "one load count per grouped kernel");
+    constexpr int ESZ = O::ESZ, CE = 16 / ESZ;
+    const int k0 = kt * Cfg::BK;
+    const bool ktail = k0 + Cfg::BK > T.k;
+#pragma unroll
+    for (int q = 0; q < O::NA; ++q) {
+        int r, c;
+        O::a_pos(q, r, c);
+        const int row = min(T.m0 + r, T.m - 1);
+        int col = k0 + c;
+        // a chunk wholly past k, or the last row's chunk that runs past k:
+        // read the row's last whole chunk
+        if (ktail && col + CE > T.k && (row == T.m - 1 || col >= T.k)) col = T.k - CE;
+        src[q] = T.A + ((int64_t)row * T.lda + col) * ESZ;
+    }
+    const bool nedge = T.n0 + Cfg::BN > T.n;
+#pragma unroll
+    for (int q = 0; q < O::NB; ++q) {
+        int kr, c;
+        O::b_pos(q, kr, c);
+        const int krow = min(k0 + kr, T.k - 1);
+        int col = T.n0 + c;
+        // a chunk wholly past n, or the last row's chunk that runs past n:
+        // read the row's last whole chunk
+        if (nedge && col + CE > T.n && (krow == T.k - 1 || col >= T.n)) col = T.n - CE;
+        src[O::NA + q] = T.B + ((int64_t)krow * T.ldb + col) * ESZ;
+    }
+}
+
+// Element-wise, masked loads of k-tile kt of a tiny tile (k or n below one
+// chunk), completed before return.
+template <class Cfg, int NV>
+__device__ __forceinline__ void gs_load_tiny(const GsTile &T, int kt, u32x4 (&v)[NV]) {
+    typedef GsOps<Cfg> O;
+    constexpr int ESZ = O::ESZ;
+    const int k0 = kt * Cfg::BK;
+#pragma unroll
+    for (int q = 0; q < O::NA; ++q) {
+        int r, c;
+        O::a_pos(q, r, c);
+        v[q] = gs_ld16_masked<ESZ>(T.A, T.lda, T.m0 + r, k0 + c, T.m, T.k);
+    }
+#pragma unroll
+    for (int q = 0; q < O::NB; ++q) {
+        int kr, c;
+        O::b_pos(q, kr, c);
+        v[O::NA + q] = gs_ld16_masked<ESZ>(T.B, T.ldb, k0 + kr, T.n0 + c, T.k, T.n);
+    }
+    wait_vmcnt_gs<0>();
+}
+
+// Fix up the edge chunks of k-tile kt of tile T after they have landed:
+// zero A past k, zero B rows past k, and shift the chunks read at a clamped
+// column into place.
+template <class Cfg, int NV>
+__device__ __forceinline__ void gs_fixup_cfg(const GsTile &T, int kt, u32x4 (&v)[NV]) {
+    typedef GsOps<Cfg> O;
+    constexpr int ESZ = O::ESZ, CE = 16 / ESZ;
+    const int k0 = kt * Cfg::BK;
+    if (k0 + Cfg::BK > T.k) {
+#pragma unroll
+        for (int q = 0; q < O::NA; ++q) {
+            int r, c;
+            O::a_pos(q, r, c);
+            const int row = min(T.m0 + r, T.m - 1);
+            const int col = k0 + c;
+            u32x4 x = v[q];
+            if (row == T.m - 1 && col + CE > T.k && col < T.k) x = gs_shift_down(x, (col - (T.k - CE)) * ESZ);
+            v[q] = gs_keep_bytes(x, max(0, min(CE, T.k - col)) * ESZ);
+        }
+#pragma unroll
+        for (int q = 0; q < O::NB; ++q) {
+            int kr, c;
+            O::b_pos(q, kr, c);
+            if (k0 + kr >= T.k) v[O::NA + q] = (u32x4){0u, 0u, 0u, 0u};
+        }
+    }
+    if (T.n0 + Cfg::BN > T.n) {
+#pragma unroll
+        for (int q = 0; q < O::NB; ++q) {
+            int kr, c;
+            O::b_pos(q, kr, c);
+            const int col = T.n0 + c;
+            if (k0 + kr == T.k - 1 && col < T.n && col + CE > T.n)
+                v[O::NA + q] = gs_shift_down(v[O::NA + q], (col - (T.n - CE)) * ESZ);
+        }
+    }
+}
+
+template <class C0, class C1>
+struct GsRing {
+    static constexpr int NV = GsOps<C0>::NA + GsOps<C0>::NB;
+    static_assert(GsOps<C1>::NA + GsOps<C1>::NB == NV, "both tiles load the same number of 16-byte vectors");
+    static constexpr int STAGE0 = C0::LDS_BYTES / 2, STAGE1 = C1::LDS_BYTES / 2;
+    static constexpr int STAGE = STAGE0 > STAGE1 ? STAGE0 : STAGE1;
+    static constexpr int ESZ = GsOps<C0>::ESZ;
+    static_assert(GsOps<C0>::ESZ == GsOps<C1>::ESZ, "one element type per grouped kernel");
+};
+
+// The stream's position: the k-tile being loaded (li, lkt) DEPTH-1 steps
+// ahead and the k-tile being multiplied (ci, ckt); `step` counts the k-tiles
+// multiplied.
+struct GsPos {
+    int li, lkt, ci, ckt, step;
+};
+
+// Issue the lookahead k-tile into ring set `v` and advance the lookahead.
+// Straight-line: every call issues exactly NV 16-byte loads, so that the
+// ring registers are only ever written by these loads (no merge of register
+// values across branches, which would make the compiler copy -- and so wait
+// for -- a set still in flight) and one vmcnt count retires the oldest set.
+// Past the end of the list, and for tiny tiles (loaded element-wise when
+// they reach the LDS), the loads read a valid dummy address.
+template <class C0, class C1, int NV>
+__device__ __forceinline__ void gs_lookahead(const GroupDesc *__restrict__ descs,
+                                             const GroupTile *__restrict__ tiles, int last, GsPos &s,
+                                             u32x4 (&v)[NV]) {
+    const bool real = s.li < last;
+    const GsTile LT = gs_tile<GsRing<C0, C1>::ESZ>(descs, tiles, real ? s.li : last - 1);
+    gs_gu8 *a0[NV], *a1[NV];
+    gs_addr_cfg<C0>(LT, s.lkt, a0);
+    gs_addr_cfg<C1>(LT, s.lkt, a1);
+    const bool use = real && !LT.tiny;
+    gs_gu8 *dummy = (gs_gu8 *)tiles;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = gs_ld16(use ? (LT.cfg == 0 ? a0[q] : a1[q]) : dummy);
+    if (real && ++s.lkt == LT.nkt) {
+        s.lkt = 0;
+        ++s.li;
+    }
+}
+
+// The k-tile kt of tile T (data in ring set `v`, already waited for; the
+// set is free afterwards) into the LDS stage `dst`.
+template <class C0, class C1, int NV>
+__device__ __forceinline__ void gs_stage(const GsTile &T, int kt, u32x4 (&v)[NV], uint8_t *dst) {
+    if (T.tiny) {
+        if (T.cfg == 0) gs_load_tiny<C0>(T, kt, v);
+        else gs_load_tiny<C1>(T, kt, v);
+    } else {
+        if (T.cfg == 0) gs_fixup_cfg<C0>(T, kt, v);
+        else gs_fixup_cfg<C1>(T, kt, v);
+    }
+    if (T.cfg == 0) GsOps<C0>::store(dst, v);
+    else GsOps<C1>::store(dst, v);
+}
+
+// One step of the stream: U is the step's position in the DEPTH-unrolled
+// loop (its register sets are ring[(U + DEPTH - 1) % DEPTH] for the issue and
+// ring[(U + 1) % DEPTH] for the next k-tile).  Returns false when the
+// workgroup's list is done.
+template <class C0, class C1, int DEPTH, int U>
+__device__ __forceinline__ bool gs_step(const GroupDesc *__restrict__ descs, const GroupTile *__restrict__ tiles,
+                                        int last, uint8_t *lds, u32x4 (&ring)[DEPTH][GsRing<C0, C1>::NV],
+                                        GsPos &s, typename GsOps<C0>::Acc &acc0, typename GsOps<C1>::Acc &acc1) {
+    typedef GsRing<C0, C1> R;
+    uint8_t *cur = lds + (s.step & 1) * R::STAGE;
+    uint8_t *nxt = lds + ((s.step + 1) & 1) * R::STAGE;
+    // 1. the k-tile DEPTH-1 steps ahead
+    gs_lookahead<C0, C1>(descs, tiles, last, s, ring[(U + DEPTH - 1) % DEPTH]);
+    // 2. the current k-tile
+    const GsTile CT = gs_tile<R::ESZ>(descs, tiles, s.ci);
+    if (CT.cfg == 0) GsOps<C0>::compute(cur, acc0);
+    else GsOps<C1>::compute(cur, acc1);
+    // 3. the next k-tile into the other LDS stage: its set is the oldest in
+    // flight, DEPTH-2 sets (all issued, real or dummy) came after it
+    const bool tile_end = s.ckt + 1 == CT.nkt;
+    const int ni = tile_end ? s.ci + 1 : s.ci;
+    const int nk = tile_end ? 0 : s.ckt + 1;
+    if (ni < last) {
+        wait_vmcnt_gs<(DEPTH - 2) * R::NV>();
+        gs_stage<C0, C1>(gs_tile<R::ESZ>(descs, tiles, ni), nk, ring[(U + 1) % DEPTH], nxt);
+    }
+    // 4. the finished tile's accumulators
+    if (tile_end) {
+        if (CT.cfg == 0) {
+            gs_epilogue<C0>(CT.C, CT.ldc, CT.m, CT.n, CT.m0, CT.n0, CT.scale, acc0);
+#pragma unroll
+            for (int rb = 0; rb < C0::RB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < C0::CB; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc0[rb][cb][r] = 0.f;
+        } else {
+            gs_epilogue<C1>(CT.C, CT.ldc, CT.m, CT.n, CT.m0, CT.n0, CT.scale, acc1);
+#pragma unroll
+            for (int rb = 0; rb < C1::RB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < C1::CB; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc1[rb][cb][r] = 0.f;
+        }
+    }
+    __syncthreads();
+    ++s.step;
+    s.ci = ni;
+    s.ckt = nk;
+    return ni < last;
+}
+
+// The persistent kernel: workgroup w walks tiles [wg_first[w], wg_first[w+1])
+// of the schedule.  C0 and C1 are register-staged tile configurations of one
+// mode (the descriptor's cfg picks one per problem).
+template <class C0, class C1, int OCC, int DEPTH>
+__global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_grouped_stream_kernel(
+    const GroupDesc *__restrict__ descs, const GroupTile *__restrict__ tiles, const int32_t *__restrict__ wg_first) {
+    static_assert(C0::THREADS == GEMM_THREADS && C1::THREADS == GEMM_THREADS, "256-lane tiles");
+    typedef GsRing<C0, C1> R;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * R::STAGE];
+    const int first = wg_first[blockIdx.x], last = wg_first[blockIdx.x + 1];
+    if (first >= last) return;
+
+    typename GsOps<C0>::Acc acc0;
+    typename GsOps<C1>::Acc acc1;
+#pragma unroll
+    for (int rb = 0; rb < C0::RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < C0::CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc0[rb][cb][r] = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < C1::RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < C1::CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc1[rb][cb][r] = 0.f;
+
+    u32x4 ring[DEPTH][R::NV];
+    GsPos s{first, 0, first, 0, 0};
+    // prologue: k-tiles 0 .. DEPTH-2 of the stream in flight, k-tile 0 in LDS
+#pragma unroll
+    for (int u = 0; u < DEPTH - 1; ++u) gs_lookahead<C0, C1>(descs, tiles, last, s, ring[u]);
+    wait_vmcnt_gs<(DEPTH - 2) * R::NV>();
+    gs_stage<C0, C1>(gs_tile<R::ESZ>(descs, tiles, first), 0, ring[0], lds);
+    __syncthreads();
+    // steady state: step j multiplies stream k-tile j (ring set j % DEPTH)
+    while (true) {
+        if (!gs_step<C0, C1, DEPTH, 0>(descs, tiles, last, lds, ring, s, acc0, acc1)) break;
+        if constexpr (DEPTH > 1)
+            if (!gs_step<C0, C1, DEPTH, 1 % DEPTH>(descs, tiles, last, lds, ring, s, acc0, acc1)) break;
+        if constexpr (DEPTH > 2)
+            if (!gs_step<C0, C1, DEPTH, 2 % DEPTH>(descs, tiles, last, lds, ring, s, acc0, acc1)) break;
+        if constexpr (DEPTH > 3)
+            if (!gs_step<C0, C1, DEPTH, 3 % DEPTH>(descs, tiles, last, lds, ring, s, acc0, acc1)) break;
+        if constexpr (DEPTH > 4)
+            if (!gs_step<C0, C1, DEPTH, 4 % DEPTH>(descs, tiles, last, lds, ring, s, acc0, acc1)) break;
+    }
+}

@@ -40,12 +40,13 @@
 //     of 16 (A) or 4-8 (B) consecutive rows hit distinct LDS banks; the
 //     swizzle is applied on the global side of the direct loads (each lane
 //     picks which logical chunk it fetches), since the LDS side is fixed.
-// Shape requirements (checked on the host; other shapes use the
-// register-staged tiles): k and n multiples of the 16-byte chunk (2 x 64-bit,
-// 4 x 32-bit, 8 x 16-bit or 16 x 8-bit), row
-// strides multiples of 16 bytes, 16-byte aligned A and B.  Rows of A beyond m
-// and columns of B beyond n read clamped (valid, finite) data whose results
-// are never stored; k beyond the end reads a zero chunk.
+// Shape requirements of the 16-byte loads (checked on the host; other shapes
+// use the register-staged tiles): k and n multiples of the 16-byte chunk
+// (2 x 64-bit, 4 x 32-bit, 8 x 16-bit or 16 x 8-bit), row strides multiples
+// of 16 bytes, 16-byte aligned A and B.  The FP32 tiles with 4-byte loads
+// (one element per lane, global_load_lds_dword) take any shape.  Rows of A
+// beyond m and columns of B beyond n read clamped (valid, finite) data whose
+// results are never stored; k beyond the end reads zeros.
 #pragma once
 
 #include <type_traits>
@@ -70,7 +71,11 @@ __device__ __forceinline__ void wait_vmcnt() {
 }
 
 // AROWB_: bytes of an A row per k-tile (0: the mode's own, 64 or 128).
-template <int MODE_, int BM_, int BN_, int STAGES_, int WM_ = 2, int WN_ = 2, int AROWB_ = 0>
+// LDB_: bytes each lane moves per direct load: 16 (global_load_lds_dwordx4;
+// k, n, strides and bases in whole 16-byte chunks) or 4 (FP32 only,
+// global_load_lds_dword: one element per lane, so any shape, stride and
+// alignment; the LDS image is the same, so are the bits).
+template <int MODE_, int BM_, int BN_, int STAGES_, int WM_ = 2, int WN_ = 2, int AROWB_ = 0, int LDB_ = 16>
 struct Lp2Cfg {
     static constexpr int MODE = MODE_;
     static constexpr int BM = BM_, BN = BN_, STAGES = STAGES_;
@@ -105,13 +110,16 @@ struct Lp2Cfg {
     static constexpr int B_STAGE = BK * B_ROWB;
     static constexpr int STAGE = A_STAGE + B_STAGE;
     static constexpr int LDS_BYTES = STAGES * STAGE;
-    static constexpr int A_LOADS = A_STAGE / 1024 / WAVES;  // direct loads per wave per k-tile
-    static constexpr int B_LOADS = B_STAGE / 1024 / WAVES;
+    static constexpr int LDB = LDB_;                    // bytes per lane per direct load
+    static constexpr int WLOAD = 64 * LDB;              // bytes one wave moves per direct load
+    static_assert(LDB == 16 || (LDB == 4 && F32), "16-byte loads, or 4-byte loads of float32 elements");
+    static constexpr int A_LOADS = A_STAGE / WLOAD / WAVES;  // direct loads per wave per k-tile
+    static constexpr int B_LOADS = B_STAGE / WLOAD / WAVES;
     static constexpr int LOADS = A_LOADS + B_LOADS;
     static_assert(RB >= 1 && CB >= 1, "wave tile");
-    static_assert(A_LOADS >= 1 && B_LOADS >= 1 && A_LOADS * 1024 * WAVES == A_STAGE &&
-                      B_LOADS * 1024 * WAVES == B_STAGE,
-                  "stage sizes must be whole numbers of one 1 KiB load per wave");
+    static_assert(A_LOADS >= 1 && B_LOADS >= 1 && A_LOADS * WLOAD * WAVES == A_STAGE &&
+                      B_LOADS * WLOAD * WAVES == B_STAGE,
+                  "stage sizes must be whole numbers of one load per wave");
     static_assert(STAGES >= 2 && (STAGES - 1) * LOADS < 64, "vmcnt range");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
     // physical chunk of logical chunk c in A row r / B row k
@@ -142,6 +150,11 @@ __device__ __forceinline__ void load_lds16(const void *src, uint32_t dst) {
     asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(dst), "v"(src) : "memory", "m0");
 }
 
+// The same with 4 bytes per lane: lane L lands at `dst` + 4 * L.
+__device__ __forceinline__ void load_lds4(const void *src, uint32_t dst) {
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, off" ::"s"(dst), "v"(src) : "memory", "m0");
+}
+
 // LDS byte address of a pointer into the workgroup's shared array, made
 // wave-uniform (one conversion per tile, not per load).
 __device__ __forceinline__ uint32_t lds_addr(const uint8_t *p) {
@@ -154,9 +167,9 @@ __device__ __forceinline__ uint32_t lds_addr(const uint8_t *p) {
 // tile: the k-tile starting at k0 then only adds k0 times the k stride.
 template <class Cfg>
 struct Lp2Src {
-    const uint8_t *a[Cfg::A_LOADS];   // A row start + logical chunk
-    int ak[Cfg::A_LOADS];             // k of that chunk within a k-tile
-    const uint8_t *b[Cfg::B_LOADS];   // B row kr of the k-tile + column chunk
+    const uint8_t *a[Cfg::A_LOADS];   // A row start + logical chunk (element)
+    int ak[Cfg::A_LOADS];             // k of that chunk (element) within a k-tile
+    const uint8_t *b[Cfg::B_LOADS];   // B row kr of the k-tile + column chunk (element)
     int bk[Cfg::B_LOADS];             // kr
     int64_t bstep;                    // bytes between consecutive B rows
     int kend;                         // loads at k >= kend read the zero chunk
@@ -170,29 +183,56 @@ __device__ __forceinline__ void lp2_sources(const TileProblem &P, int m0, int n0
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint8_t *A = static_cast<const uint8_t *>(P.A);
     const uint8_t *B = static_cast<const uint8_t *>(P.B);
+    if constexpr (Cfg::LDB == 16) {
 #pragma unroll
-    for (int j = 0; j < Cfg::A_LOADS; ++j) {
-        const int t = wave * Cfg::A_LOADS + j;          // 1 KiB piece of the A stage
-        const int r = (64 / Cfg::A_CPR) * t + lane / Cfg::A_CPR;   // tile row
-        const int c = (lane % Cfg::A_CPR) ^ Cfg::a_swz(r);           // logical chunk at physical chunk lane % A_CPR
-        const int row = min(m0 + r, P.m - 1);
-        S.ak[j] = c * Cfg::CE;
-        S.a[j] = A + ((int64_t)row * P.lda + S.ak[j]) * Cfg::ESZ;
-    }
+        for (int j = 0; j < Cfg::A_LOADS; ++j) {
+            const int t = wave * Cfg::A_LOADS + j;          // 1 KiB piece of the A stage
+            const int r = (64 / Cfg::A_CPR) * t + lane / Cfg::A_CPR;   // tile row
+            const int c = (lane % Cfg::A_CPR) ^ Cfg::a_swz(r);           // logical chunk at physical chunk lane % A_CPR
+            const int row = min(m0 + r, P.m - 1);
+            S.ak[j] = c * Cfg::CE;
+            S.a[j] = A + ((int64_t)row * P.lda + S.ak[j]) * Cfg::ESZ;
+        }
 #pragma unroll
-    for (int j = 0; j < Cfg::B_LOADS; ++j) {
-        const int slot = 64 * (wave * Cfg::B_LOADS + j) + lane;
-        const int kr = slot / Cfg::B_CPR;
-        const int c = (slot % Cfg::B_CPR) ^ Cfg::b_swz(kr);
-        const int n = min(n0 + c * Cfg::CE, P.n - Cfg::CE);
-        S.bk[j] = kr;
-        S.b[j] = B + ((int64_t)kr * P.ldb + n) * Cfg::ESZ;
+        for (int j = 0; j < Cfg::B_LOADS; ++j) {
+            const int slot = 64 * (wave * Cfg::B_LOADS + j) + lane;
+            const int kr = slot / Cfg::B_CPR;
+            const int c = (slot % Cfg::B_CPR) ^ Cfg::b_swz(kr);
+            const int n = min(n0 + c * Cfg::CE, P.n - Cfg::CE);
+            S.bk[j] = kr;
+            S.b[j] = B + ((int64_t)kr * P.ldb + n) * Cfg::ESZ;
+        }
+    } else {
+        // 4-byte loads: lane L of load j writes stage byte WLOAD * (the wave's
+        // piece j) + 4 L, i.e. one element of a row's physical 16-byte chunk;
+        // it fetches that element of the logical chunk the swizzle puts there
+#pragma unroll
+        for (int j = 0; j < Cfg::A_LOADS; ++j) {
+            const int byte = Cfg::WLOAD * (wave * Cfg::A_LOADS + j) + Cfg::LDB * lane;
+            const int r = byte / Cfg::A_ROWB;                                   // tile row
+            const int o = byte % Cfg::A_ROWB;
+            const int c = (o / 16) ^ Cfg::a_swz(r);                             // logical chunk
+            const int row = min(m0 + r, P.m - 1);
+            S.ak[j] = c * Cfg::CE + (o % 16) / Cfg::ESZ;
+            S.a[j] = A + ((int64_t)row * P.lda + S.ak[j]) * Cfg::ESZ;
+        }
+#pragma unroll
+        for (int j = 0; j < Cfg::B_LOADS; ++j) {
+            const int byte = Cfg::WLOAD * (wave * Cfg::B_LOADS + j) + Cfg::LDB * lane;
+            const int kr = byte / Cfg::B_ROWB;
+            const int o = byte % Cfg::B_ROWB;
+            const int c = (o / 16) ^ Cfg::b_swz(kr);
+            // columns past n: a valid element whose products are never stored
+            const int n = min(n0 + c * Cfg::CE + (o % 16) / Cfg::ESZ, P.n - 1);
+            S.bk[j] = kr;
+            S.b[j] = B + ((int64_t)kr * P.ldb + n) * Cfg::ESZ;
+        }
     }
     S.bstep = P.ldb * Cfg::ESZ;
     S.kend = kend;
     const uint32_t base = lds_addr(lds);
-    S.dst_a = base + 1024 * (wave * Cfg::A_LOADS);
-    S.dst_b = base + Cfg::A_STAGE + 1024 * (wave * Cfg::B_LOADS);
+    S.dst_a = base + Cfg::WLOAD * (wave * Cfg::A_LOADS);
+    S.dst_b = base + Cfg::A_STAGE + Cfg::WLOAD * (wave * Cfg::B_LOADS);
 }
 
 // Issue direct load j (A loads first, then B) of this wave for the k-tile
@@ -204,12 +244,14 @@ __device__ __forceinline__ void lp2_issue_one(const Lp2Src<Cfg> &S, int k0, uint
     if (j < Cfg::A_LOADS) {
         const void *src = (!CHECK || k0 + S.ak[j] < S.kend) ? (const void *)(S.a[j] + (int64_t)k0 * Cfg::ESZ)
                                                              : (const void *)g_zero_chunk;
-        load_lds16(src, S.dst_a + soff + 1024 * j);
+        if constexpr (Cfg::LDB == 16) load_lds16(src, S.dst_a + soff + Cfg::WLOAD * j);
+        else load_lds4(src, S.dst_a + soff + Cfg::WLOAD * j);
     } else {
         const int b = j - Cfg::A_LOADS;
         const void *src = (!CHECK || k0 + S.bk[b] < S.kend) ? (const void *)(S.b[b] + (int64_t)k0 * S.bstep)
                                                              : (const void *)g_zero_chunk;
-        load_lds16(src, S.dst_b + soff + 1024 * b);
+        if constexpr (Cfg::LDB == 16) load_lds16(src, S.dst_b + soff + Cfg::WLOAD * b);
+        else load_lds4(src, S.dst_b + soff + Cfg::WLOAD * b);
     }
 }
 
@@ -612,8 +654,8 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
     }
 }
 
-template <int MODE, int BM, int BN, int STAGES, int WM, int WN, int AROWB>
-__device__ __forceinline__ void Lp2Cfg<MODE, BM, BN, STAGES, WM, WN, AROWB>::run(const TileProblem &P, int tm, int tn,
-                                                                           int split, uint8_t *lds) {
-    lp2_tile<Lp2Cfg<MODE, BM, BN, STAGES, WM, WN, AROWB>>(P, tm, tn, split, lds);
+template <int MODE, int BM, int BN, int STAGES, int WM, int WN, int AROWB, int LDB>
+__device__ __forceinline__ void Lp2Cfg<MODE, BM, BN, STAGES, WM, WN, AROWB, LDB>::run(const TileProblem &P, int tm,
+                                                                                int tn, int split, uint8_t *lds) {
+    lp2_tile<Lp2Cfg<MODE, BM, BN, STAGES, WM, WN, AROWB, LDB>>(P, tm, tn, split, lds);
 }

@@ -59,6 +59,8 @@ F32_CASES = [
     (50000, 45056, 32, 0, 8, 13, 1),           # asynchronous copy, k-tiles of 16
     (33001, 33003, 96, 0, 5, 3, 3),            # split-K: the third partial slab starts past 2^31
     (33000, 33004, 96, 0, 8, 15, 3),           # the same on an asynchronous-copy tile
+    (50001, 45003, 20, 45011, 5, 25, 1),       # asynchronous copy with 4-byte loads, ragged; A is 9 GB
+    (33001, 33003, 96, 0, 5, 26, 3),           # the same (64 x 64), split-K slab past 2^31
 ]
 
 
@@ -80,7 +82,7 @@ def test_f32_past_2_31(m, n, k, pad_a, pad_c, cfg, split):
     _free()
 
 
-@pytest.mark.parametrize("cfg", [None, 20])
+@pytest.mark.parametrize("cfg", [None, 20, 25])
 def test_f32_b_rows_past_2_31(cfg):
     """B rows 2^26 + 64 elements apart: row 32 onwards starts past element
     2^31 of B's allocation (12.9 GB)."""
