@@ -236,13 +236,15 @@ int gemm_errnorm(const float *C, int64_t ldc, const double *R, int64_t ldr,
 /* decomposition (one thread block per output tile, Fig. 5) across         */
 /* problems, with one queue of tiles over all of them.                     */
 
-/* All problems must share one mode (F32 or BF16/F16/F8E4M3/split); each
- * problem's tile configuration is a function of its mode and shape only
- * (the tuning table's grouped entries, else a cost model), so its bits do
- * not depend on the other problems, and equal gemm_plain's with split_k = 1.
- * The problem list is copied; the device descriptors and the work-queue
- * counters belong to the (device, stream) pair, so calls on different
- * streams run independently, and calls on one stream are ordered by it. */
+/* All problems must share one mode (F32 or BF16/F16/F8E4M3/split).  Each
+ * problem runs on one of the grouped kernel's two tiles (the cost model's
+ * choice for its shape, or the small tile when the launch would not fill
+ * the chip); every tile of a mode gives the same bits, so a problem's result
+ * does not depend on the other problems and equals gemm_plain's with
+ * split_k = 1.  The host builds a static schedule (gemm_grouped_schedule)
+ * and uploads it with the descriptors into the (device, stream) pair's
+ * workspace, so calls on different streams run independently, and calls on
+ * one stream are ordered by it. */
 int gemm_grouped(const gemm_problem_t *ps, int32_t count, void *stream);
 
 /* The grouped kernel of `mode`: info[0..3] = {first tile configuration,
@@ -251,10 +253,12 @@ int gemm_grouped(const gemm_problem_t *ps, int32_t count, void *stream);
 int gemm_grouped_info(int32_t mode, int32_t info[4]);
 
 /* The tile configuration a problem of this shape gets in a grouped launch
- * (out[0]) and as a launch of its own in the server (out[1]), and out[2] = 1
- * when both come from measured entries of the tuning table (0: cost model).
- * A launch whose problems would not fill every resident-workgroup slot runs
- * all of them on the smaller tile instead (see gemm_grouped_plan). */
+ * (out[0]: the cost model with the mode's calibrated small-tile efficiency)
+ * and as a launch of its own in the server (out[1]: the bucket's measured
+ * choice, else the model), and out[2] = 1 when both come from measurements
+ * (0: the model's defaults).  A launch whose problems would not fill every
+ * resident-workgroup slot runs all of them on the smaller tile instead (see
+ * gemm_grouped_plan). */
 int gemm_grouped_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t out[3]);
 
 /* The tile configuration each problem of this list gets in gemm_grouped
@@ -298,14 +302,20 @@ int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
  * without an exact entry; the split factor is kept as requested, and each
  * shape of the bucket normalises it to its own k. */
 int gemm_tune_bucket(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
-/* Measure the grouped kernel's two tiles on this shape and record, for its
- * bucket, the faster one in a batch (a grouped launch of enough identical
- * problems, each with its own operands, to fill every resident-workgroup
- * slot twice; at most 256 problems and 1 GiB) and the faster one alone (a
- * launch of one problem); medians of seven event-timed launches on non-zero
- * operands.  Synchronises.  Dimensions up to 65536.  Errors: GEMM_EINVAL,
- * GEMM_EUNSUPPORTED, GEMM_ENOMEM, GEMM_EHIP. */
+/* Measure the grouped kernel's two tiles on a problem of this shape launched
+ * alone (medians of seven event-timed launches on non-zero operands the
+ * library allocates) and record the faster for the shape's bucket: the tile
+ * a serving batch of one gets.  Synchronises.  Dimensions up to 65536.
+ * Errors: GEMM_EINVAL, GEMM_EUNSUPPORTED, GEMM_ENOMEM, GEMM_EHIP. */
 int gemm_tune_grouped(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
+/* Calibrate, on the caller's mixed problem list (one mode, device operands
+ * the caller owns; C is overwritten), the cost model that picks each
+ * problem's tile in a grouped launch: the small tile's efficiency relative
+ * to the large one is varied over a grid, each resulting plan is timed
+ * (median of seven launches, two passes), and the fastest is recorded for
+ * the mode; the default (0.6) is kept unless another is more than 1 %
+ * faster.  Synchronises.  Errors: as gemm_grouped, plus GEMM_EHIP. */
+int gemm_tune_grouped_mix(const gemm_problem_t *ps, int32_t count, void *stream);
 /* The (cfg, split_k) gemm_plain would use for this shape: the exact entry,
  * else the bucket entry, else the cost model. */
 int gemm_tuner_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t *cfg, int32_t *split_k);

@@ -108,6 +108,7 @@ _SIGS = {
     "gemm_tune": (c_int32, [c_int32, c_int64, c_int64, c_int64, c_void_p]),
     "gemm_tune_bucket": (c_int32, [c_int32, c_int64, c_int64, c_int64, c_void_p]),
     "gemm_tune_grouped": (c_int32, [c_int32, c_int64, c_int64, c_int64, c_void_p]),
+    "gemm_tune_grouped_mix": (c_int32, [_P, c_int32, c_void_p]),
     "gemm_tuner_lookup": (c_int32, [c_int32, c_int64, c_int64, c_int64, POINTER(c_int32), POINTER(c_int32)]),
     "gemm_tuner_load": (c_int32, [c_char_p]),
     "gemm_tuner_save": (c_int32, [c_char_p]),

@@ -23,6 +23,13 @@ static const KernelCfg kTable[] = {
     make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 2, 2, 4, 128>, 2, 8>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 2, 4, 2, 128>, 2, 8>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 256, 2, 2, 2, 128>, 1, 8>(),
+    // 16x16x32 MFMA blocks (same bits as the 32x32x16 tiles): four waves
+    // on 256 x 128 and 128 x 256 (one per SIMD), and 128 x 128 with k-tiles
+    // of 32 (four stages) or 64 (two)
+    make_cfg<Lp2Cfg<GEMM_MODE_F16, 256, 128, 4, 2, 2, 0, 16, 16>, 1, 8>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F16, 128, 256, 4, 2, 2, 0, 16, 16>, 1, 8>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F16, 128, 128, 4, 2, 2, 0, 16, 16>, 2, 8>(),
+    make_cfg<Lp2Cfg<GEMM_MODE_F16, 128, 128, 2, 2, 2, 128, 16, 16>, 2, 8>(),
 };
 
 const KernelCfg *lp_configs_f16(int *count) {

@@ -14,11 +14,14 @@
 
 namespace mg {
 
-// Per-problem choice between the grouped kernel's two tile configurations:
-// the tuning table's measured choice for the problem's shape bucket, else a
-// cost model that weighs the padded tile area against the lower sustained
-// rate of the small tile.
-static int grouped_model(int mode, int64_t m, int64_t n, bool alone) {
+// Default efficiency of the small tile relative to the large one in the
+// cost model, where the tuning table has no measured value for the mode.
+static const double kDefaultSmallEff = 0.6;
+
+// Cost model of the choice between the grouped kernel's two tile
+// configurations: the padded tile area, weighed by the small tile's lower
+// sustained rate (`small_eff`); alone, in rounds of resident workgroups.
+static int grouped_model(int mode, int64_t m, int64_t n, bool alone, double small_eff) {
     const GroupedKernel *gk = grouped_kernel(mode);
     int count = 0;
     const KernelCfg *t = configs(mode, &count);
@@ -27,7 +30,7 @@ static int grouped_model(int mode, int64_t m, int64_t n, bool alone) {
     for (int c = 0; c < 2; ++c) {
         const KernelCfg &kc = t[gk->cfg_idx[c]];
         const double tiles = (double)((m + kc.bm - 1) / kc.bm) * (double)((n + kc.bn - 1) / kc.bn);
-        const double eff = (kc.bm * kc.bn >= 16384) ? 1.0 : 0.6;
+        const double eff = (kc.bm * kc.bn >= 16384) ? 1.0 : small_eff;
         // alone, rounds of resident workgroups count: a mid-size product on
         // the large tile would leave most CUs idle
         const double slots = (double)num_cus() * std::max(1, gk->wg_per_cu);
@@ -40,18 +43,31 @@ static int grouped_model(int mode, int64_t m, int64_t n, bool alone) {
     return pick;
 }
 
+// Set by gemm_tune_grouped_mix while it plans its candidates.
+static thread_local double t_eff_override = -1.0;
+
+static double small_eff_of(int mode) {
+    if (t_eff_override > 0) return t_eff_override;
+    const double e = tuner_grouped_eff(mode);
+    return e > 0 ? e : kDefaultSmallEff;
+}
+
+// In a batch: the cost model with the small-tile efficiency the autotuner
+// measured on a mixed batch (gemm_tune_grouped_mix).  Per-shape choices
+// measured on batches of one shape chose the small tile where a mixed batch
+// runs faster on the large one, so the batch choice is the calibrated model.
 int grouped_choose(int mode, int64_t m, int64_t n, int64_t k) {
-    int in_batch = 0, alone = 0;
-    if (tuner_grouped_choice(mode, m, n, k, &in_batch, &alone)) return in_batch;
-    return grouped_model(mode, m, n, false);
+    (void)k;
+    return grouped_model(mode, m, n, false, small_eff_of(mode));
 }
 
 // The same choice for a problem launched on its own (a serving batch of one):
-// the two tiles give the same bits, so the one that finishes first is taken.
+// the two tiles give the same bits, so the one measured to finish first for
+// the shape's bucket is taken, else the model's.
 int grouped_choose_alone(int mode, int64_t m, int64_t n, int64_t k) {
-    int in_batch = 0, alone = 0;
-    if (tuner_grouped_choice(mode, m, n, k, &in_batch, &alone)) return alone;
-    return grouped_model(mode, m, n, true);
+    int alone = 0;
+    if (tuner_grouped_alone(mode, m, n, k, &alone)) return alone;
+    return grouped_model(mode, m, n, true, small_eff_of(mode));
 }
 
 const GroupedKernel *grouped_kernel(int mode) {
@@ -427,77 +443,105 @@ int gemm_tune_grouped(int32_t mode, int64_t m, int64_t n, int64_t k, void *strea
     if (m > 65536 || n > 65536 || k > 65536) return fail(GEMM_EUNSUPPORTED, "tuning shapes are limited to 65536");
     const GroupedKernel *gk = grouped_kernel(mode);
     if (!gk) return fail(GEMM_EUNSUPPORTED, "mode %d has no grouped kernel", mode);
-    int tcount = 0;
-    const KernelCfg *t = configs(mode, &tcount);
     hipStream_t s = (hipStream_t)stream;
     const int64_t es = (int64_t)elem_size(mode);
-    // A batch of identical problems, enough that the option with fewer tiles
-    // fills every resident-workgroup slot twice (at most 256 problems and
-    // 1 GiB of operands), each with operands of its own.
-    int64_t fewest = INT64_MAX;
-    for (int o = 0; o < 2; ++o) {
-        const KernelCfg &kc = t[gk->cfg_idx[o]];
-        fewest = std::min<int64_t>(fewest, ((m + kc.bm - 1) / kc.bm) * ((n + kc.bn - 1) / kc.bn));
-    }
-    const int64_t slots = (int64_t)num_cus() * std::max(1, gk->wg_per_cu);
-    int64_t count = std::min<int64_t>(256, std::max<int64_t>(1, (2 * slots + fewest - 1) / fewest));
     const int64_t abytes = (m * k * es + 255) / 256 * 256, bbytes = (k * n * es + 255) / 256 * 256,
                   cbytes = (m * n * 4 + 255) / 256 * 256;
-    const int64_t per = abytes + bbytes + cbytes;
-    while (count > 1 && count * per > ((int64_t)1 << 30)) count = (count + 1) / 2;
     uint8_t *buf = nullptr;
-    void *image = nullptr;
-    if (hipMalloc(&buf, (size_t)(count * per)) != hipSuccess) {
+    if (hipMalloc(&buf, (size_t)(abytes + bbytes + cbytes)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GEMM_ENOMEM, "grouped tuning buffers do not fit");
     }
-    std::vector<gemm_problem_t> ps((size_t)count);
-    for (int64_t i = 0; i < count; ++i) {
-        gemm_problem_t &p = ps[(size_t)i];
-        memset(&p, 0, sizeof(p));
-        uint8_t *base = buf + i * per;
-        p.mode = mode;
-        p.m = m;
-        p.n = n;
-        p.k = k;
-        p.A = base;
-        p.lda = k;
-        p.B = base + abytes;
-        p.ldb = n;
-        p.C = reinterpret_cast<float *>(base + abytes + bbytes);
-        p.ldc = n;
-        p.scale_a = p.scale_b = 1.f;
-    }
+    gemm_problem_t p;
+    memset(&p, 0, sizeof(p));
+    p.mode = mode;
+    p.m = m;
+    p.n = n;
+    p.k = k;
+    p.A = buf;
+    p.lda = k;
+    p.B = buf + abytes;
+    p.ldb = n;
+    p.C = reinterpret_cast<float *>(buf + abytes + bbytes);
+    p.ldc = n;
+    p.scale_a = p.scale_b = 1.f;
     int rc = GEMM_OK;
     // non-zero operands: the clock under load depends on the data
-    if (launch_fill_tuning(buf, count * per / es, (int)es, 3u, s) != hipSuccess)
+    if (launch_fill_tuning(buf, (abytes + bbytes + cbytes) / es, (int)es, 3u, s) != hipSuccess)
         rc = fail(GEMM_EHIP, "filling the tuning operands failed");
-    float batch_ms[2] = {0.f, 0.f}, alone_ms[2] = {0.f, 0.f};
-    for (int o = 0; o < 2 && rc == GEMM_OK; ++o) {
-        GroupPlan plan;
-        rc = build_group_plan(ps.data(), (int32_t)count, plan, o);
-        if (rc != GEMM_OK) break;
-        const size_t bytes = plan_image_bytes(plan);
-        std::vector<uint8_t> host(bytes);
-        plan_image_write(plan, host.data());
-        if (image) (void)hipFree(image);
-        image = nullptr;
-        if (hipMalloc(&image, bytes) != hipSuccess ||
-            hipMemcpy(image, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipGetLastError();
-            rc = fail(GEMM_EHIP, "grouped tuning descriptors");
-            break;
-        }
-        rc = time_median(s, 7, [&] { return enqueue_group(plan, image, s); },
-                         &batch_ms[o]);
-        if (rc != GEMM_OK) break;
-        rc = time_median(s, 7, [&] { return enqueue_plain(ps[0], gk->cfg_idx[o], 1, nullptr, s); }, &alone_ms[o]);
-    }
+    float alone_ms[2] = {0.f, 0.f};
+    for (int o = 0; o < 2 && rc == GEMM_OK; ++o)
+        rc = time_median(s, 7, [&] { return enqueue_plain(p, gk->cfg_idx[o], 1, nullptr, s); }, &alone_ms[o]);
     if (rc == GEMM_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(GEMM_EHIP, "stream sync failed");
-    if (image) (void)hipFree(image);
     (void)hipFree(buf);
     if (rc != GEMM_OK) return rc;
-    tuner_record_grouped(mode, m, n, k, batch_ms[1] < batch_ms[0] ? 1 : 0, alone_ms[1] < alone_ms[0] ? 1 : 0);
+    tuner_record_grouped(mode, m, n, k, alone_ms[1] < alone_ms[0] ? 1 : 0);
+    return GEMM_OK;
+}
+
+int gemm_tune_grouped_mix(const gemm_problem_t *ps, int32_t count, void *stream) {
+    clear_error();
+    if (count <= 0 || !ps) return fail(GEMM_EINVAL, "tuning needs a non-empty problem list");
+    GroupPlan check;
+    int rc = build_group_plan(ps, count, check);
+    if (rc != GEMM_OK) return rc;
+    if (check.total_tiles == 0) return fail(GEMM_EINVAL, "tuning needs a non-empty product");
+    const int mode = check.mode;
+    hipStream_t s = (hipStream_t)stream;
+    // candidate efficiencies of the small tile; the model's default is one
+    // of them, and a candidate replaces it only if it is more than 1 % faster
+    static const double grid[] = {0.3, 0.45, kDefaultSmallEff, 0.75, 0.9, 1.0, 1.25, 1.6};
+    const int ng = (int)(sizeof(grid) / sizeof(grid[0]));
+    std::vector<std::vector<GroupDesc>> seen;
+    std::vector<int> plan_of(ng, -1);
+    std::vector<float> best_ms;
+    void *image = nullptr;
+    for (int pass = 0; pass < 2 && rc == GEMM_OK; ++pass) {
+        for (int g = 0; g < ng && rc == GEMM_OK; ++g) {
+            t_eff_override = grid[g];
+            GroupPlan plan;
+            rc = build_group_plan(ps, count, plan);
+            t_eff_override = -1.0;
+            if (rc != GEMM_OK) break;
+            // candidates that give the same tile choices share one timing
+            int id = -1;
+            for (size_t j = 0; j < seen.size(); ++j) {
+                bool same = seen[j].size() == plan.descs.size();
+                for (size_t i = 0; same && i < plan.descs.size(); ++i) same = seen[j][i].cfg == plan.descs[i].cfg;
+                if (same) id = (int)j;
+            }
+            if (id < 0) {
+                id = (int)seen.size();
+                seen.push_back(plan.descs);
+                best_ms.push_back(1e30f);
+            }
+            plan_of[g] = id;
+            const size_t bytes = plan_image_bytes(plan);
+            std::vector<uint8_t> host(bytes);
+            plan_image_write(plan, host.data());
+            if (image) (void)hipFree(image);
+            image = nullptr;
+            if (hipMalloc(&image, bytes) != hipSuccess ||
+                hipMemcpy(image, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+                (void)hipGetLastError();
+                rc = fail(GEMM_EHIP, "grouped tuning descriptors");
+                break;
+            }
+            float ms = 0.f;
+            rc = time_median(s, 7, [&] { return enqueue_group(plan, image, s); }, &ms);
+            if (rc == GEMM_OK) best_ms[id] = std::min(best_ms[id], ms);
+        }
+    }
+    t_eff_override = -1.0;
+    if (rc == GEMM_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(GEMM_EHIP, "stream sync failed");
+    if (image) (void)hipFree(image);
+    if (rc != GEMM_OK) return rc;
+    int def = 0;
+    while (def < ng && grid[def] != kDefaultSmallEff) ++def;
+    int pick = def;
+    for (int g = 0; g < ng; ++g)
+        if (best_ms[plan_of[g]] < 0.99f * best_ms[plan_of[pick]]) pick = g;
+    tuner_record_grouped_eff(mode, grid[pick]);
     return GEMM_OK;
 }
 
@@ -521,8 +565,8 @@ int gemm_grouped_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t o
     if (m < 0 || n < 0 || k < 0) return fail(GEMM_EINVAL, "negative dimension");
     const GroupedKernel *gk = grouped_kernel(mode);
     if (!gk) return fail(GEMM_EUNSUPPORTED, "mode %d has no grouped kernel", mode);
-    int in_batch = 0, alone = 0;
-    const bool measured = tuner_grouped_choice(mode, m, n, k, &in_batch, &alone);
+    int alone = 0;
+    const bool measured = tuner_grouped_alone(mode, m, n, k, &alone) && tuner_grouped_eff(mode) > 0;
     out[0] = gk->cfg_idx[grouped_choose(mode, m, n, k)];
     out[1] = gk->cfg_idx[grouped_choose_alone(mode, m, n, k)];
     out[2] = measured ? 1 : 0;

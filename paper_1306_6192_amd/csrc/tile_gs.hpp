@@ -32,6 +32,8 @@
 // of elements) take element-wise loads and a full wait instead.
 #pragma once
 
+#include <type_traits>
+
 #include "tile_f32.hpp"
 #include "tile_lp.hpp"
 
@@ -338,6 +340,7 @@ struct GsRing {
     static constexpr int STAGE = STAGE0 > STAGE1 ? STAGE0 : STAGE1;
     static constexpr int ESZ = GsOps<C0>::ESZ;
     static_assert(GsOps<C0>::ESZ == GsOps<C1>::ESZ, "one element type per grouped kernel");
+    static constexpr bool ONE = std::is_same<C0, C1>::value;   // one tile configuration
 };
 
 // The stream's position: the k-tile being loaded (li, lkt) DEPTH-1 steps
@@ -366,7 +369,7 @@ __device__ __forceinline__ void gs_lookahead(const GroupDesc *__restrict__ descs
     const bool use = real && !LT.tiny;
     gs_gu8 *dummy = (gs_gu8 *)tiles;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = gs_ld16(use ? (LT.cfg == 0 ? a0[q] : a1[q]) : dummy);
+    for (int q = 0; q < NV; ++q) v[q] = gs_ld16(use ? (GsRing<C0, C1>::ONE || LT.cfg == 0 ? a0[q] : a1[q]) : dummy);
     if (real && ++s.lkt == LT.nkt) {
         s.lkt = 0;
         ++s.li;
@@ -378,13 +381,13 @@ __device__ __forceinline__ void gs_lookahead(const GroupDesc *__restrict__ descs
 template <class C0, class C1, int NV>
 __device__ __forceinline__ void gs_stage(const GsTile &T, int kt, u32x4 (&v)[NV], uint8_t *dst) {
     if (T.tiny) {
-        if (T.cfg == 0) gs_load_tiny<C0>(T, kt, v);
+        if (GsRing<C0, C1>::ONE || T.cfg == 0) gs_load_tiny<C0>(T, kt, v);
         else gs_load_tiny<C1>(T, kt, v);
     } else {
-        if (T.cfg == 0) gs_fixup_cfg<C0>(T, kt, v);
+        if (GsRing<C0, C1>::ONE || T.cfg == 0) gs_fixup_cfg<C0>(T, kt, v);
         else gs_fixup_cfg<C1>(T, kt, v);
     }
-    if (T.cfg == 0) GsOps<C0>::store(dst, v);
+    if (GsRing<C0, C1>::ONE || T.cfg == 0) GsOps<C0>::store(dst, v);
     else GsOps<C1>::store(dst, v);
 }
 
@@ -403,7 +406,7 @@ __device__ __forceinline__ bool gs_step(const GroupDesc *__restrict__ descs, con
     gs_lookahead<C0, C1>(descs, tiles, last, s, ring[(U + DEPTH - 1) % DEPTH]);
     // 2. the current k-tile
     const GsTile CT = gs_tile<R::ESZ>(descs, tiles, s.ci);
-    if (CT.cfg == 0) GsOps<C0>::compute(cur, acc0);
+    if (R::ONE || CT.cfg == 0) GsOps<C0>::compute(cur, acc0);
     else GsOps<C1>::compute(cur, acc1);
     // 3. the next k-tile into the other LDS stage: its set is the oldest in
     // flight, DEPTH-2 sets (all issued, real or dummy) came after it
@@ -416,7 +419,7 @@ __device__ __forceinline__ bool gs_step(const GroupDesc *__restrict__ descs, con
     }
     // 4. the finished tile's accumulators
     if (tile_end) {
-        if (CT.cfg == 0) {
+        if (R::ONE || CT.cfg == 0) {
             gs_epilogue<C0>(CT.C, CT.ldc, CT.m, CT.n, CT.m0, CT.n0, CT.scale, acc0);
 #pragma unroll
             for (int rb = 0; rb < C0::RB; ++rb)

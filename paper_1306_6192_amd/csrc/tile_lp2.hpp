@@ -75,7 +75,12 @@ __device__ __forceinline__ void wait_vmcnt() {
 // k, n, strides and bases in whole 16-byte chunks) or 4 (FP32 only,
 // global_load_lds_dword: one element per lane, so any shape, stride and
 // alignment; the LDS image is the same, so are the bits).
-template <int MODE_, int BM_, int BN_, int STAGES_, int WM_ = 2, int WN_ = 2, int AROWB_ = 0, int LDB_ = 16>
+// MB_: accumulator block edge of the 16-bit tiles: 32 (v_mfma_f32_32x32x16,
+// k-steps of 16) or 16 (v_mfma_f32_16x16x32, k-steps of 32; one such MFMA
+// gives the bits of two 32x32x16 MFMAs over its two k halves, so both tile
+// families of a mode give the same results).
+template <int MODE_, int BM_, int BN_, int STAGES_, int WM_ = 2, int WN_ = 2, int AROWB_ = 0, int LDB_ = 16,
+          int MB_ = 32>
 struct Lp2Cfg {
     static constexpr int MODE = MODE_;
     static constexpr int BM = BM_, BN = BN_, STAGES = STAGES_;
@@ -85,7 +90,10 @@ struct Lp2Cfg {
     static constexpr bool F32 = (MODE == GEMM_MODE_F32);
     static constexpr bool F64 = (MODE == GEMM_MODE_F64);
     static constexpr bool C32 = (MODE == GEMM_MODE_C32);
-    static constexpr int BLK = F64 ? 16 : 32;           // accumulator block edge
+    static constexpr bool H16 = (MODE == GEMM_MODE_BF16 || MODE == GEMM_MODE_F16);
+    static_assert(MB_ == 32 || (MB_ == 16 && H16), "16x16 blocks for the 16-bit tiles only");
+    static constexpr bool M16 = H16 && MB_ == 16;      // 16x16x32 MFMAs
+    static constexpr int BLK = F64 ? 16 : MB_;          // accumulator block edge
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int RB = TM / BLK, CB = TN / BLK;
     static constexpr int CBA = C32 ? 2 * CB : CB;       // accumulator blocks per row block
@@ -96,14 +104,14 @@ struct Lp2Cfg {
     static constexpr int BK = A_ROWB / ESZ;             // k per k-tile
     // k per step: one MFMA (16- and 8-bit), four 32x32x2 MFMAs (FP32), four
     // 16x16x4 MFMAs (binary64), four times four 32x32x2 MFMAs (complex)
-    static constexpr int KCH = (MODE == GEMM_MODE_F8E4M3) ? 64 : F64 ? 16 : (F32 || C32) ? 8 : 16;
+    static constexpr int KCH = (MODE == GEMM_MODE_F8E4M3) ? 64 : F64 ? 16 : (F32 || C32) ? 8 : M16 ? 32 : 16;
     static constexpr int MFMA_K = (F32 || C32) ? 2 : F64 ? 4 : KCH;
     static constexpr int STEPS = BK / KCH;
     static constexpr bool FOUR = F32 || F64 || C32;     // four k-slots per block per step
     static constexpr int NPB = FOUR ? 4 : CB;           // B fragment reads per step
     static constexpr int NP = RB + NPB;                 // fragment reads per step
     static constexpr int NM = RB * CB * (FOUR ? 4 : 1) * (C32 ? 4 : 1);   // MFMAs per step
-    typedef typename std::conditional<F64, f64x4, f32x16>::type Acc;
+    typedef typename std::conditional<F64, f64x4, typename std::conditional<M16, f32x4, f32x16>::type>::type Acc;
     static constexpr int B_ROWB = BN * ESZ;
     static constexpr int B_CPR = B_ROWB / 16;           // 16-byte chunks per B row
     static constexpr int A_STAGE = BM * A_ROWB;
@@ -375,6 +383,27 @@ __device__ __forceinline__ void lp2_read_piece(const uint8_t *stage, int kc, int
             }
             F.b[cb] = (i32x8){q[0][0], q[0][1], q[1][0], q[1][1], q[2][0], q[2][1], q[3][0], q[3][1]};
         }
+    } else if constexpr (Cfg::M16) {
+        // 16x16x32: lane (l%16, G = l/16) holds k = 8G .. 8G + 7 of row l%16
+        // (A) and of column l%16 (B) of the step's 32 k
+        if (p < Cfg::RB) {
+            const int rb = p;
+            const int r = wm * Cfg::TM + rb * 16 + p16;
+            F.a[rb] = *reinterpret_cast<const u32x4 *>(As + r * Cfg::A_ROWB + 16 * ((4 * kc + G) ^ Cfg::a_swz(r)));
+        } else {
+            const int cb = p - Cfg::RB;
+            const int n = wn * Cfg::TN + cb * 16 + 4 * (p16 & 3);
+            s16x4 hv[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = 32 * kc + 8 * G + 4 * h + (p16 >> 2);
+                const uint8_t *a = Bs + k * Cfg::B_ROWB + 16 * ((n >> 3) ^ Cfg::b_swz(k)) + 2 * (n & 7);
+                hv[h] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4 *)a);
+            }
+            const i32x2 lo = __builtin_bit_cast(i32x2, hv[0]);
+            const i32x2 hi = __builtin_bit_cast(i32x2, hv[1]);
+            F.b[cb] = (u32x4){(uint32_t)lo[0], (uint32_t)lo[1], (uint32_t)hi[0], (uint32_t)hi[1]};
+        }
     } else {
         if (p < Cfg::RB) {
             const int rb = p;
@@ -445,6 +474,12 @@ __device__ __forceinline__ void lp2_mfma1(const Lp2Frag<Cfg> &F, typename Cfg::A
         if constexpr (Cfg::MODE == GEMM_MODE_F8E4M3)
             acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(F.a[rb], F.b[cb], acc[rb][cb], 0, 0, 0,
                                                                          0, 0, 0);
+        else if constexpr (Cfg::M16 && Cfg::MODE == GEMM_MODE_BF16)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, F.a[rb]), __builtin_bit_cast(bf16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
+        else if constexpr (Cfg::M16)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                __builtin_bit_cast(f16x8, F.a[rb]), __builtin_bit_cast(f16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
         else if constexpr (Cfg::MODE == GEMM_MODE_BF16)
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                 __builtin_bit_cast(bf16x8, F.a[rb]), __builtin_bit_cast(bf16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
@@ -452,6 +487,30 @@ __device__ __forceinline__ void lp2_mfma1(const Lp2Frag<Cfg> &F, typename Cfg::A
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                 __builtin_bit_cast(f16x8, F.a[rb]), __builtin_bit_cast(f16x8, F.b[cb]), acc[rb][cb], 0, 0, 0);
     }
+}
+
+// Epilogue of the 16x16 blocks: lane l, register i of block (rb, cb) holds
+// row 16 rb + 4 (l/16) + i, column 16 cb + l%16 of the wave's tile.
+template <class Cfg>
+__device__ __forceinline__ void lp2_epilogue16(float *__restrict__ C, int64_t ldc, int M, int N, int m0, int n0,
+                                               float scale, const f32x4 (&acc)[Cfg::RB][Cfg::CB]) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
+    const int p16 = lane & 15, G = lane >> 4;
+#pragma unroll
+    for (int rb = 0; rb < Cfg::RB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = m0 + wm * Cfg::TM + rb * 16 + 4 * G + i;
+            if (row >= M) continue;
+            float *p = C + (int64_t)row * ldc;
+#pragma unroll
+            for (int cb = 0; cb < Cfg::CB; ++cb) {
+                const int col = n0 + wn * Cfg::TN + cb * 16 + p16;
+                if (col < N) p[col] = acc[rb][cb][i] * scale;
+            }
+        }
 }
 
 // Natural-column epilogue: lane l%32 of accumulator block cb holds output
@@ -650,12 +709,14 @@ __device__ __forceinline__ void lp2_tile(const TileProblem &P, int tm, int tn, i
         float scale;
         epilogue_target(P, split, C, ldc, scale);
         if constexpr (Cfg::F32) tile_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
+        else if constexpr (Cfg::M16) lp2_epilogue16<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
         else lp2_epilogue<Cfg>(C, ldc, P.m, P.n, m0, n0, scale, acc);
     }
 }
 
-template <int MODE, int BM, int BN, int STAGES, int WM, int WN, int AROWB, int LDB>
-__device__ __forceinline__ void Lp2Cfg<MODE, BM, BN, STAGES, WM, WN, AROWB, LDB>::run(const TileProblem &P, int tm,
-                                                                                int tn, int split, uint8_t *lds) {
-    lp2_tile<Lp2Cfg<MODE, BM, BN, STAGES, WM, WN, AROWB, LDB>>(P, tm, tn, split, lds);
+template <int MODE, int BM, int BN, int STAGES, int WM, int WN, int AROWB, int LDB, int MB>
+__device__ __forceinline__ void Lp2Cfg<MODE, BM, BN, STAGES, WM, WN, AROWB, LDB, MB>::run(const TileProblem &P,
+                                                                                    int tm, int tn, int split,
+                                                                                    uint8_t *lds) {
+    lp2_tile<Lp2Cfg<MODE, BM, BN, STAGES, WM, WN, AROWB, LDB, MB>>(P, tm, tn, split, lds);
 }

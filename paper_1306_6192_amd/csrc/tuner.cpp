@@ -27,7 +27,8 @@ typedef std::tuple<int, int, int, int> BKey;   // mode, log2 buckets of m, n, k
 static std::mutex g_mu;
 static std::map<Key, std::pair<int, int>> g_table;          // exact shape -> (cfg, split)
 static std::map<BKey, std::pair<int, int>> g_plain_bucket;  // bucket -> (cfg, split)
-static std::map<BKey, std::pair<int, int>> g_grouped;       // bucket -> (option in a batch, option alone)
+static std::map<BKey, int> g_grouped;                       // bucket -> option alone
+static double g_grouped_eff[GEMM_NUM_MODES] = {-1, -1, -1, -1, -1};   // small-tile efficiency (< 0: unset)
 static bool g_env_loaded = false;
 
 int dim_bucket(int64_t d) {
@@ -131,26 +132,37 @@ void tuner_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg, int *spli
     heuristic_choose(mode, m, n, k, cfg, split);
 }
 
-bool tuner_grouped_choice(int mode, int64_t m, int64_t n, int64_t k, int *in_batch, int *alone) {
+bool tuner_grouped_alone(int mode, int64_t m, int64_t n, int64_t k, int *alone) {
     std::lock_guard<std::mutex> lk(g_mu);
     load_env_locked();
     auto it = g_grouped.find(bucket_of(mode, m, n, k));
     if (it == g_grouped.end()) return false;
-    *in_batch = it->second.first;
-    *alone = it->second.second;
+    *alone = it->second;
     return true;
 }
 
-void tuner_record_grouped(int mode, int64_t m, int64_t n, int64_t k, int in_batch, int alone) {
+void tuner_record_grouped(int mode, int64_t m, int64_t n, int64_t k, int alone) {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_grouped[bucket_of(mode, m, n, k)] = {in_batch, alone};
+    g_grouped[bucket_of(mode, m, n, k)] = alone;
 }
 
-// One JSON object per line, in one of three forms (the forms gemm_tuner_save
+double tuner_grouped_eff(int mode) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_env_locked();
+    return mode_known(mode) ? g_grouped_eff[mode] : -1.0;
+}
+
+void tuner_record_grouped_eff(int mode, double eff) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (mode_known(mode)) g_grouped_eff[mode] = eff;
+}
+
+// One JSON object per line, in one of four forms (the forms gemm_tuner_save
 // writes; lines in any other form are skipped):
 //   {"mode": M, "m": m, "n": n, "k": k, "cfg": C, "split": S}
 //   {"bucket": "plain", "mode": M, "bm": a, "bn": b, "bk": c, "cfg": C, "split": S}
-//   {"bucket": "grouped", "mode": M, "bm": a, "bn": b, "bk": c, "tile": T, "alone": U}
+//   {"bucket": "grouped", "mode": M, "bm": a, "bn": b, "bk": c, "alone": U}
+//   {"grouped_eff": M, "eff": E}
 static int load_file_locked(const char *path) {
     FILE *f = fopen(path, "r");
     if (!f) return fail(GEMM_ENOTFOUND, "cannot open tuning file %s", path);
@@ -180,11 +192,24 @@ static int load_file_locked(const char *path) {
             }
         } else if (sscanf(line,
                           " {\"bucket\": \"grouped\", \"mode\": %d, \"bm\": %d, \"bn\": %d, \"bk\": %d, "
+                          "\"alone\": %d",
+                          &mode, &bm, &bn, &bk, &cfg) == 5 ||
+                   sscanf(line,
+                          " {\"bucket\": \"grouped\", \"mode\": %d, \"bm\": %d, \"bn\": %d, \"bk\": %d, "
                           "\"tile\": %d, \"alone\": %d",
-                          &mode, &bm, &bn, &bk, &cfg, &split) == 6) {
-            if (!mode_known(mode) || cfg < 0 || cfg > 1 || split < 0 || split > 1) continue;
-            g_grouped[BKey(mode, bm, bn, bk)] = {cfg, split};
+                          &mode, &bm, &bn, &bk, &split, &cfg) == 6) {
+            // (the second form also carries an in-batch tile, which the
+            // calibrated cost model now decides; only the alone choice is kept)
+            if (!mode_known(mode) || cfg < 0 || cfg > 1) continue;
+            g_grouped[BKey(mode, bm, bn, bk)] = cfg;
             ++n_ok;
+        } else {
+            double eff = 0;
+            if (sscanf(line, " {\"grouped_eff\": %d, \"eff\": %lf", &mode, &eff) == 2 && mode_known(mode) &&
+                eff > 0 && eff <= 4) {
+                g_grouped_eff[mode] = eff;
+                ++n_ok;
+            }
         }
     }
     fclose(f);
@@ -258,11 +283,11 @@ int gemm_tuner_save(const char *path) {
                 std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
                 kv.second.first, kv.second.second);
     for (auto &kv : g_grouped)
-        fprintf(f,
-                "{\"bucket\": \"grouped\", \"mode\": %d, \"bm\": %d, \"bn\": %d, \"bk\": %d, \"tile\": %d, "
-                "\"alone\": %d}\n",
+        fprintf(f, "{\"bucket\": \"grouped\", \"mode\": %d, \"bm\": %d, \"bn\": %d, \"bk\": %d, \"alone\": %d}\n",
                 std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
-                kv.second.first, kv.second.second);
+                kv.second);
+    for (int m = 0; m < GEMM_NUM_MODES; ++m)
+        if (g_grouped_eff[m] > 0) fprintf(f, "{\"grouped_eff\": %d, \"eff\": %.3f}\n", m, g_grouped_eff[m]);
     fclose(f);
     return GEMM_OK;
 }

@@ -12,8 +12,13 @@ Three kinds of entries (each chosen by the library's own timing):
 * ``plain-buckets``: the same measurement on one representative shape per
   log2 bucket of (m, n, k) (``gemm_tune_bucket``), consulted for every shape
   without an exact entry;
-* ``grouped``: the grouped kernel's tile per bucket, in a batch and alone
-  (``gemm_tune_grouped``).
+* ``grouped``: the grouped kernel's tile per bucket for a problem launched
+  alone (``gemm_tune_grouped``), and the small-tile efficiency of the cost
+  model that picks tiles in a batch, calibrated on a mixed batch of seeded
+  synthetic problems (``gemm_tune_grouped_mix``): 512 problems with m, n, k
+  log-uniform in [32, 1024] (the grouped workload's distribution, another
+  seed) for FP32, BF16, F16 and split-BF16x3, and 48 problems with m, n, k
+  log-uniform in [64, 4096] (a serving batch) for E4M3.
 
 Buckets cover the grouped workload (dims log-uniform in [32, 1024], FP32 and
 BF16) and the serving workload (dims log-uniform in [64, 4096], FP32, BF16
@@ -76,10 +81,32 @@ def bucket_shapes(mg):
     return out
 
 
+def calibrate_mix(mg, _lib, lib, torch, mode, count, lo, hi, stream):
+    """gemm_tune_grouped_mix on `count` seeded problems with dims log-uniform
+    in [lo, hi] (seed 100, not the benchmark's), operands uniform[-1, 1]
+    on the device in the mode's element type."""
+    import synth
+    g = torch.Generator(device="cuda").manual_seed(100)
+    ops = []
+    for m, n, k in synth.loguniform_dims(count, lo, hi, seed=100).tolist():
+        a = torch.rand((m, k), device="cuda", generator=g) * 2 - 1
+        b = torch.rand((k, n), device="cuda", generator=g) * 2 - 1
+        if mode in (mg.MODE_BF16, mg.MODE_F16):
+            a, b = mg.convert(a, mode), mg.convert(b, mode)
+        elif mode == mg.MODE_F8E4M3:
+            a, _ = mg.quantize_e4m3(a)
+            b, _ = mg.quantize_e4m3(b)
+        ops.append((a, b, torch.empty((m, n), device="cuda")))
+    probs = [mg.make_problem(a, b, c, mode) for a, b, c in ops]
+    torch.cuda.synchronize()
+    _lib.check(lib.gemm_tune_grouped_mix(_lib.problems_array(probs), len(probs), stream))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_TABLE)
     ap.add_argument("--what", default="exact,plain-buckets,grouped")
+    ap.add_argument("--modes", default="", help="comma-separated mode names to tune (default: all)")
     args = ap.parse_args(argv)
     what = set(args.what.split(","))
     import torch
@@ -94,18 +121,32 @@ def main(argv=None):
     def save():
         _lib.check(lib.gemm_tuner_save(args.out.encode()))
 
+    keep = {mode for mode, name in mg.MODE_NAMES.items() if not args.modes or name in args.modes.split(",")}
     if "exact" in what:
         for mode, (m, n, k) in exact_shapes(mg):
+            if mode not in keep:
+                continue
             cfg, split = mg.tune(mode, m, n, k)
             info = mg.config_info(mode, cfg)
             print(f"{mg.MODE_NAMES[mode]:>13} {m}x{n}x{k}: cfg {cfg} ({info['BM']}x{info['BN']}x{info['BK']}) "
                   f"split {split}", flush=True)
+        save()
+    if "grouped" in what:
+        mixes = {mg.MODE_F32: (512, 32, 1024), mg.MODE_BF16: (512, 32, 1024), mg.MODE_F16: (512, 32, 1024),
+                 mg.MODE_SPLIT_BF16X3: (512, 32, 1024), mg.MODE_F8E4M3: (48, 64, 4096)}
+        for mode, (count, lo, hi) in mixes.items():
+            if mode not in keep:
+                continue
+            calibrate_mix(mg, _lib, lib, torch, mode, count, lo, hi, stream)
+            print(f"grouped mix {mg.MODE_NAMES[mode]}: small-tile efficiency calibrated", flush=True)
         save()
     buckets = bucket_shapes(mg)
     for kind, entry in (("plain-buckets", lib.gemm_tune_bucket), ("grouped", lib.gemm_tune_grouped)):
         if kind not in what:
             continue
         for mode, shapes in buckets.items():
+            if mode not in keep:
+                continue
             t0 = time.time()
             for i, (m, n, k) in enumerate(shapes):
                 _lib.check(entry(mode, m, n, k, stream))

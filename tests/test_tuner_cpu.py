@@ -1,6 +1,6 @@
 """Host logic of the autotuner, the grouped planner and the workspace
 accounting, without a GPU: table lookups (exact, bucket, grouped), the
-planner taking the table's tile choice, the grouped kernels' occupancy plan
+planner taking the table's calibrated efficiency and alone choices, the grouped kernels' occupancy plan
 against the LDS they allocate, and the workspace a plain launch needs."""
 import ctypes
 import os
@@ -141,35 +141,58 @@ def test_bucket_entry_serves_unmeasured_shapes(tmp_path):
 
 
 def test_grouped_planner_takes_the_table_choice(tmp_path):
-    """A measured grouped entry decides the tile of every problem in its
-    bucket, in a batch and alone, against the cost model's choice."""
+    """In a batch the planner takes the cost model's tile under the small-tile
+    efficiency the table holds for the mode (a measured "grouped_eff" line);
+    alone it takes the bucket's measured tile.  Both tiles give the same
+    bits, so only the speed depends on these entries."""
     mode = _lib.MODE_F16
     cfg0, cfg1, wg_per_cu, _ = grouped_info(mode)
-    m, n, k = 3000, 2900, 40000          # large: the model takes the large tile
+    small = cfg1 if config_info(mode, cfg1)[0] * config_info(mode, cfg1)[1] < \
+        config_info(mode, cfg0)[0] * config_info(mode, cfg0)[1] else cfg0
+    large = cfg0 + cfg1 - small
+    m, n, k = 3000, 2900, 40000          # k outside every tuned bucket
     before = grouped_lookup(mode, m, n, k)
     assert before[2] == 0
     f = tmp_path / "g.jsonl"
-    flip_batch = 1 if before[0] == cfg0 else 0
-    flip_alone = 1 if before[1] == cfg0 else 0
-    f.write_text('{"bucket": "grouped", "mode": %d, "bm": %d, "bn": %d, "bk": %d, "tile": %d, "alone": %d}\n'
-                 % (mode, bucket(m), bucket(n), bucket(k), flip_batch, flip_alone))
-    _lib.check(_lib.load().gemm_tuner_load(str(f).encode()))
-    after = grouped_lookup(mode, m, n, k)
-    assert after[2] == 1
-    assert after[0] == (cfg0, cfg1)[flip_batch] and after[0] != before[0]
-    assert after[1] == (cfg0, cfg1)[flip_alone]
-    # the planner gives that tile to every problem of the bucket; a problem of
-    # another bucket keeps the model's choice; an empty output gets none
+    lib = _lib.load()
     probs = [prob(mode, m, n, k, A=A_PTR + i * (1 << 34), B=B_PTR + i * (1 << 34), C=C_PTR + i * (1 << 34))
              for i in range(3)]
     other = prob(mode, 700, 900, 300, A=A_PTR + 5 * (1 << 34), B=B_PTR + 5 * (1 << 34), C=C_PTR + 5 * (1 << 34))
     empty = prob(mode, 0, 900, 300, A=A_PTR + 6 * (1 << 34), B=B_PTR + 6 * (1 << 34), C=C_PTR + 6 * (1 << 34))
     arr = _lib.problems_array(probs + [other, empty])
-    out = (ctypes.c_int32 * 5)()
-    _lib.check(_lib.load().gemm_grouped_plan(arr, 5, out))
-    assert list(out[:3]) == [after[0]] * 3
-    assert out[3] == grouped_lookup(mode, 700, 900, 300)[0]
-    assert out[4] == -1
+    try:
+        # padded area: 2162 small tiles of 64x64 against 552 large of 128x128;
+        # at efficiency 4 the small tile costs a quarter, at 0.05 twenty times
+        for eff, want in ((4.0, small), (0.05, large)):
+            f.write_text('{"grouped_eff": %d, "eff": %.3f}\n' % (mode, eff))
+            _lib.check(lib.gemm_tuner_load(str(f).encode()))
+            assert grouped_lookup(mode, m, n, k)[0] == want, eff
+            out = (ctypes.c_int32 * 5)()
+            _lib.check(lib.gemm_grouped_plan(arr, 5, out))
+            assert list(out[:3]) == [want] * 3, eff
+            assert out[3] == grouped_lookup(mode, 700, 900, 300)[0]
+            assert out[4] == -1
+        # an efficiency outside (0, 4] is not loaded
+        f.write_text('{"grouped_eff": %d, "eff": 9.0}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(f).encode()))
+        assert grouped_lookup(mode, m, n, k)[0] == large
+        # alone: the bucket's measured tile, in the current form and in the
+        # older form that also carried an in-batch tile (ignored now)
+        for flip, line in ((0, '"alone": %d'), (1, '"tile": 0, "alone": %d'), (0, '"tile": 1, "alone": %d')):
+            alone = (cfg0, cfg1)[flip]
+            f.write_text(('{"bucket": "grouped", "mode": %d, "bm": %d, "bn": %d, "bk": %d, ' + line + '}\n')
+                         % (mode, bucket(m), bucket(n), bucket(k), flip))
+            _lib.check(lib.gemm_tuner_load(str(f).encode()))
+            after = grouped_lookup(mode, m, n, k)
+            assert after[1] == alone and after[2] == 1
+            assert after[0] == large
+    finally:
+        # back to the default efficiency, then the shipped table's entries
+        f.write_text('{"grouped_eff": %d, "eff": 0.600}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(f).encode()))
+        shipped = os.path.join(ROOT, "paper_1306_6192_amd", "tuning", "mi355x.jsonl")
+        if os.path.exists(shipped):
+            _lib.check(lib.gemm_tuner_load(shipped.encode()))
 
 
 def test_grouped_lookup_and_plan_validate():
