@@ -418,9 +418,9 @@ def section_grouped(args, torch, mg, synth, stream, line, jobs=None):
             ops.append((a, b, torch.empty((A.shape[0], B.shape[1]), device="cuda")))
         torch.cuda.synchronize()
         graph = mg.GroupedGraph(ops, mode=mode)
-        t_graph = T.time(lambda: graph.launch(stream), 10, warmup=2)
+        t_graph = T.time(lambda: graph.launch(stream), 20, warmup=2, warm_ms=WARM_MS)
         batch = mg.ProblemBatch(ops, mode=mode)   # problem array built once, as a caller would
-        t_grouped = T.time(lambda: batch.run(stream), 10, warmup=2)
+        t_grouped = T.time(lambda: batch.run(stream), 20, warmup=2, warm_ms=WARM_MS)
 
         def plain_all():
             for a, b, c in ops:

@@ -211,7 +211,7 @@ struct GsTile {
     int cfg;        // 0 or 1
     int m0, n0;
     int nkt;        // k-tiles of the tile's configuration (at least 1)
-    bool tiny;      // k or n below one 16-byte chunk: element-wise loads
+    int tiny;       // k or n below one 16-byte chunk: element-wise loads
 };
 
 template <int ESZ>
@@ -236,6 +236,20 @@ __device__ __forceinline__ GsTile gs_tile(const GroupDesc *__restrict__ descs, c
     T.nkt = e.nkt;
     T.tiny = T.k < 16 / ESZ || T.n < 16 / ESZ;
     return T;
+}
+
+// What the multiply cursor keeps of its tile from one k-tile to the next
+// (the bounds the staging needs); the operands and C are read from the
+// schedule where they are needed (tiny tiles, the epilogue).
+struct GsCur {
+    int m, n, k, m0, n0, cfg, nkt, tiny;
+};
+
+template <int ESZ>
+__device__ __forceinline__ GsCur gs_cur(const GroupDesc *__restrict__ descs, const GroupTile *__restrict__ tiles,
+                                        int i) {
+    const GsTile T = gs_tile<ESZ>(descs, tiles, i);
+    return GsCur{T.m, T.n, T.k, T.m0, T.n0, T.cfg, T.nkt, T.tiny};
 }
 
 // Source addresses of the NV loads of k-tile kt of tile T for configuration
@@ -297,8 +311,8 @@ __device__ __forceinline__ void gs_load_tiny(const GsTile &T, int kt, u32x4 (&v)
 // Fix up the edge chunks of k-tile kt of tile T after they have landed:
 // zero A past k, zero B rows past k, and shift the chunks read at a clamped
 // column into place.
-template <class Cfg, int NV>
-__device__ __forceinline__ void gs_fixup_cfg(const GsTile &T, int kt, u32x4 (&v)[NV]) {
+template <class Cfg, class TT, int NV>
+__device__ __forceinline__ void gs_fixup_cfg(const TT &T, int kt, u32x4 (&v)[NV]) {
     typedef GsOps<Cfg> O;
     constexpr int ESZ = O::ESZ, CE = 16 / ESZ;
     const int k0 = kt * Cfg::BK;
@@ -343,12 +357,31 @@ struct GsRing {
     static constexpr bool ONE = std::is_same<C0, C1>::value;   // one tile configuration
 };
 
-// The stream's position: the k-tile being loaded (li, lkt) DEPTH-1 steps
-// ahead and the k-tile being multiplied (ci, ckt); `step` counts the k-tiles
-// multiplied.
-struct GsPos {
+// The stream's state: the lookahead cursor (li, lkt: the next k-tile to
+// load; LT: its tile; src: the per-lane addresses of the k-tile it loaded
+// last) runs DEPTH-1 k-tiles ahead of the multiply cursor (ci, ckt; CT: its
+// tile); `step` counts the k-tiles multiplied.  A cursor reads its tile's
+// record from the schedule only when it enters the tile.
+template <int NV>
+struct GsState {
     int li, lkt, ci, ckt, step;
+    GsTile LT;
+    GsCur CT;
+    gs_gu8 *src[NV];
 };
+
+// Advance the addresses of the NV loads by one k-tile (an interior k-tile:
+// no bound depends on k there, so each address moves by the k-tile's
+// stride: BK elements along an A row, BK rows down B).
+template <class Cfg, int NV>
+__device__ __forceinline__ void gs_advance_cfg(const GsTile &T, gs_gu8 *(&src)[NV]) {
+    typedef GsOps<Cfg> O;
+#pragma unroll
+    for (int q = 0; q < O::NA; ++q) src[q] += Cfg::BK * O::ESZ;
+    const int64_t bstep = (int64_t)Cfg::BK * T.ldb * O::ESZ;
+#pragma unroll
+    for (int q = 0; q < O::NB; ++q) src[O::NA + q] += bstep;
+}
 
 // Issue the lookahead k-tile into ring set `v` and advance the lookahead.
 // Straight-line: every call issues exactly NV 16-byte loads, so that the
@@ -356,33 +389,45 @@ struct GsPos {
 // values across branches, which would make the compiler copy -- and so wait
 // for -- a set still in flight) and one vmcnt count retires the oldest set.
 // Past the end of the list, and for tiny tiles (loaded element-wise when
-// they reach the LDS), the loads read a valid dummy address.
+// they reach the LDS), the loads read a valid dummy address.  The addresses
+// are computed in full at a tile's first and last k-tile and advanced by
+// one k-tile in between.
 template <class C0, class C1, int NV>
 __device__ __forceinline__ void gs_lookahead(const GroupDesc *__restrict__ descs,
-                                             const GroupTile *__restrict__ tiles, int last, GsPos &s,
+                                             const GroupTile *__restrict__ tiles, int last, GsState<NV> &s,
                                              u32x4 (&v)[NV]) {
+    typedef GsRing<C0, C1> R;
     const bool real = s.li < last;
-    const GsTile LT = gs_tile<GsRing<C0, C1>::ESZ>(descs, tiles, real ? s.li : last - 1);
-    gs_gu8 *a0[NV], *a1[NV];
-    gs_addr_cfg<C0>(LT, s.lkt, a0);
-    gs_addr_cfg<C1>(LT, s.lkt, a1);
-    const bool use = real && !LT.tiny;
+    if (real) {
+        const bool first_cfg = R::ONE || s.LT.cfg == 0;
+        if (s.lkt == 0 || s.lkt + 1 == s.LT.nkt) {
+            if (first_cfg) gs_addr_cfg<C0>(s.LT, s.lkt, s.src);
+            else gs_addr_cfg<C1>(s.LT, s.lkt, s.src);
+        } else {
+            if (first_cfg) gs_advance_cfg<C0>(s.LT, s.src);
+            else gs_advance_cfg<C1>(s.LT, s.src);
+        }
+    }
+    const bool use = real && !s.LT.tiny;
     gs_gu8 *dummy = (gs_gu8 *)tiles;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = gs_ld16(use ? (GsRing<C0, C1>::ONE || LT.cfg == 0 ? a0[q] : a1[q]) : dummy);
-    if (real && ++s.lkt == LT.nkt) {
+    for (int q = 0; q < NV; ++q) v[q] = gs_ld16(use ? s.src[q] : dummy);
+    if (real && ++s.lkt == s.LT.nkt) {
         s.lkt = 0;
-        ++s.li;
+        if (++s.li < last) s.LT = gs_tile<R::ESZ>(descs, tiles, s.li);
     }
 }
 
-// The k-tile kt of tile T (data in ring set `v`, already waited for; the
-// set is free afterwards) into the LDS stage `dst`.
+// The k-tile kt of tile i of the schedule (bounds in `T`; data in ring set
+// `v`, already waited for; the set is free afterwards) into the LDS stage
+// `dst`.  Tiny tiles read their operands element-wise here.
 template <class C0, class C1, int NV>
-__device__ __forceinline__ void gs_stage(const GsTile &T, int kt, u32x4 (&v)[NV], uint8_t *dst) {
+__device__ __forceinline__ void gs_stage(const GroupDesc *__restrict__ descs, const GroupTile *__restrict__ tiles,
+                                         int i, const GsCur &T, int kt, u32x4 (&v)[NV], uint8_t *dst) {
     if (T.tiny) {
-        if (GsRing<C0, C1>::ONE || T.cfg == 0) gs_load_tiny<C0>(T, kt, v);
-        else gs_load_tiny<C1>(T, kt, v);
+        const GsTile F = gs_tile<GsRing<C0, C1>::ESZ>(descs, tiles, i);
+        if (GsRing<C0, C1>::ONE || T.cfg == 0) gs_load_tiny<C0>(F, kt, v);
+        else gs_load_tiny<C1>(F, kt, v);
     } else {
         if (GsRing<C0, C1>::ONE || T.cfg == 0) gs_fixup_cfg<C0>(T, kt, v);
         else gs_fixup_cfg<C1>(T, kt, v);
@@ -398,27 +443,29 @@ __device__ __forceinline__ void gs_stage(const GsTile &T, int kt, u32x4 (&v)[NV]
 template <class C0, class C1, int DEPTH, int U>
 __device__ __forceinline__ bool gs_step(const GroupDesc *__restrict__ descs, const GroupTile *__restrict__ tiles,
                                         int last, uint8_t *lds, u32x4 (&ring)[DEPTH][GsRing<C0, C1>::NV],
-                                        GsPos &s, typename GsOps<C0>::Acc &acc0, typename GsOps<C1>::Acc &acc1) {
+                                        GsState<GsRing<C0, C1>::NV> &s, typename GsOps<C0>::Acc &acc0,
+                                        typename GsOps<C1>::Acc &acc1) {
     typedef GsRing<C0, C1> R;
     uint8_t *cur = lds + (s.step & 1) * R::STAGE;
     uint8_t *nxt = lds + ((s.step + 1) & 1) * R::STAGE;
     // 1. the k-tile DEPTH-1 steps ahead
     gs_lookahead<C0, C1>(descs, tiles, last, s, ring[(U + DEPTH - 1) % DEPTH]);
+    const bool tile_end = s.ckt + 1 == s.CT.nkt;
+    const int ni = tile_end ? s.ci + 1 : s.ci;
+    const int nk = tile_end ? 0 : s.ckt + 1;
+    // the next tile's bounds (read while the current k-tile is multiplied)
+    GsCur NT = s.CT;
+    if (tile_end && ni < last) NT = gs_cur<R::ESZ>(descs, tiles, ni);
     // 2. the current k-tile
-    const GsTile CT = gs_tile<R::ESZ>(descs, tiles, s.ci);
-    if (R::ONE || CT.cfg == 0) GsOps<C0>::compute(cur, acc0);
+    if (R::ONE || s.CT.cfg == 0) GsOps<C0>::compute(cur, acc0);
     else GsOps<C1>::compute(cur, acc1);
     // 3. the next k-tile into the other LDS stage: its set is the oldest in
     // flight, DEPTH-2 sets (all issued, real or dummy) came after it
-    const bool tile_end = s.ckt + 1 == CT.nkt;
-    const int ni = tile_end ? s.ci + 1 : s.ci;
-    const int nk = tile_end ? 0 : s.ckt + 1;
-    if (ni < last) {
-        wait_vmcnt_gs<(DEPTH - 2) * R::NV>();
-        gs_stage<C0, C1>(gs_tile<R::ESZ>(descs, tiles, ni), nk, ring[(U + 1) % DEPTH], nxt);
-    }
+    wait_vmcnt_gs<(DEPTH - 2) * R::NV>();
+    if (ni < last) gs_stage<C0, C1>(descs, tiles, ni, NT, nk, ring[(U + 1) % DEPTH], nxt);
     // 4. the finished tile's accumulators
     if (tile_end) {
+        const GsTile CT = gs_tile<R::ESZ>(descs, tiles, s.ci);
         if (R::ONE || CT.cfg == 0) {
             gs_epilogue<C0>(CT.C, CT.ldc, CT.m, CT.n, CT.m0, CT.n0, CT.scale, acc0);
 #pragma unroll
@@ -436,7 +483,13 @@ __device__ __forceinline__ bool gs_step(const GroupDesc *__restrict__ descs, con
 #pragma unroll
                     for (int r = 0; r < 16; ++r) acc1[rb][cb][r] = 0.f;
         }
+        s.CT = NT;
     }
+    // keep this step's set (staged one step ago, reloaded by the next step)
+    // live until the reload, so that its registers are not lent to
+    // temporaries, which would have to wait for its load
+#pragma unroll
+    for (int q = 0; q < R::NV; ++q) asm volatile("" ::"v"(ring[U % DEPTH][q]));
     __syncthreads();
     ++s.step;
     s.ci = ni;
@@ -472,12 +525,18 @@ __global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_grouped_stream_kernel(
             for (int r = 0; r < 16; ++r) acc1[rb][cb][r] = 0.f;
 
     u32x4 ring[DEPTH][R::NV];
-    GsPos s{first, 0, first, 0, 0};
+    GsState<R::NV> s;
+    s.li = s.ci = first;
+    s.lkt = s.ckt = s.step = 0;
+    s.LT = gs_tile<R::ESZ>(descs, tiles, first);
+    s.CT = gs_cur<R::ESZ>(descs, tiles, first);
+#pragma unroll
+    for (int q = 0; q < R::NV; ++q) s.src[q] = (gs_gu8 *)tiles;
     // prologue: k-tiles 0 .. DEPTH-2 of the stream in flight, k-tile 0 in LDS
 #pragma unroll
     for (int u = 0; u < DEPTH - 1; ++u) gs_lookahead<C0, C1>(descs, tiles, last, s, ring[u]);
     wait_vmcnt_gs<(DEPTH - 2) * R::NV>();
-    gs_stage<C0, C1>(gs_tile<R::ESZ>(descs, tiles, first), 0, ring[0], lds);
+    gs_stage<C0, C1>(descs, tiles, first, s.CT, 0, ring[0], lds);
     __syncthreads();
     // steady state: step j multiplies stream k-tile j (ring set j % DEPTH)
     while (true) {
