@@ -236,29 +236,31 @@ int gemm_errnorm(const float *C, int64_t ldc, const double *R, int64_t ldr,
 /* decomposition (one thread block per output tile, Fig. 5) across         */
 /* problems, with one queue of tiles over all of them.                     */
 
-/* All problems must share one mode (F32 or BF16/F16/F8E4M3/split).  Each
- * problem runs on one of the grouped kernel's two tiles (the cost model's
- * choice for its shape, or the small tile when the launch would not fill
- * the chip); every tile of a mode gives the same bits, so a problem's result
- * does not depend on the other problems and equals gemm_plain's with
- * split_k = 1.  The host builds a static schedule (gemm_grouped_schedule)
+/* All problems must share one mode (F32 or BF16/F16/F8E4M3/split).  Every
+ * problem runs on the grouped kernel's tile (128 x 128; a kernel built with
+ * two tiles picks one per problem by the cost model, or the smaller one when
+ * the launch would not fill the chip); every tile of a mode gives the same
+ * bits, so a problem's result does not depend on the other problems and
+ * equals gemm_plain's with split_k = 1.  The host builds a static schedule (gemm_grouped_schedule)
  * and uploads it with the descriptors into the (device, stream) pair's
  * workspace, so calls on different streams run independently, and calls on
  * one stream are ordered by it. */
 int gemm_grouped(const gemm_problem_t *ps, int32_t count, void *stream);
 
-/* The grouped kernel of `mode`: info[0..3] = {first tile configuration,
- * second tile configuration (indices into gemm_config_info), resident
- * workgroups per CU, LDS bytes per workgroup}. */
-int gemm_grouped_info(int32_t mode, int32_t info[4]);
+/* The grouped kernel of `mode`: info[0..5] = {first and second tile
+ * configuration of its stream (indices into gemm_config_info; equal when it
+ * runs one), resident workgroups per CU, LDS bytes per workgroup, the larger
+ * and the smaller configuration a problem launched on its own may take}. */
+int gemm_grouped_info(int32_t mode, int32_t info[6]);
 
 /* The tile configuration a problem of this shape gets in a grouped launch
- * (out[0]: the cost model with the mode's calibrated small-tile efficiency)
- * and as a launch of its own in the server (out[1]: the bucket's measured
- * choice, else the model), and out[2] = 1 when both come from measurements
- * (0: the model's defaults).  A launch whose problems would not fill every
- * resident-workgroup slot runs all of them on the smaller tile instead (see
- * gemm_grouped_plan). */
+ * (out[0]: the stream's tile, or for a two-tile stream the cost model's
+ * choice with the mode's calibrated small-tile efficiency) and as a launch
+ * of its own in the server (out[1]: the bucket's measured choice between the
+ * two configurations of gemm_grouped_info's info[4..5], else the model),
+ * and out[2] = 1 when both come from measurements (0: the model's defaults).
+ * A two-tile launch whose problems would not fill every resident-workgroup
+ * slot runs all of them on the smaller tile instead (see gemm_grouped_plan). */
 int gemm_grouped_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t out[3]);
 
 /* The tile configuration each problem of this list gets in gemm_grouped
@@ -302,15 +304,16 @@ int gemm_tune(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
  * without an exact entry; the split factor is kept as requested, and each
  * shape of the bucket normalises it to its own k. */
 int gemm_tune_bucket(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
-/* Measure the grouped kernel's two tiles on a problem of this shape launched
- * alone (medians of seven event-timed launches on non-zero operands the
+/* Measure the two configurations a problem launched alone may take
+ * (gemm_grouped_info's info[4..5]) on a problem of this shape (medians of seven event-timed launches on non-zero operands the
  * library allocates) and record the faster for the shape's bucket: the tile
  * a serving batch of one gets.  Synchronises.  Dimensions up to 65536.
  * Errors: GEMM_EINVAL, GEMM_EUNSUPPORTED, GEMM_ENOMEM, GEMM_EHIP. */
 int gemm_tune_grouped(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
 /* Calibrate, on the caller's mixed problem list (one mode, device operands
  * the caller owns; C is overwritten), the cost model that picks each
- * problem's tile in a grouped launch: the small tile's efficiency relative
+ * problem's tile in a grouped launch of a two-tile stream (a one-tile stream
+ * has nothing to pick; the default is then recorded): the small tile's efficiency relative
  * to the large one is varied over a grid, each resulting plan is timed
  * (median of seven launches, two passes), and the fastest is recorded for
  * the mode; the default (0.6) is kept unless another is more than 1 %

@@ -1,7 +1,7 @@
 // F16 product kernels: the plain launch for every tile configuration
 // (register-staged tiles for any shape; asynchronous-copy tiles for shapes
 // whose k, n and row strides are whole 16-byte chunks) and the grouped
-// persistent launch (128x128 and 64x64 tiles).
+// persistent launch (128x128 tiles; 128x128 or 64x64 for a problem alone).
 #include "kernels_impl.hpp"
 #include "tile_lp.hpp"
 #include "tile_lp2.hpp"
@@ -38,6 +38,7 @@ const KernelCfg *lp_configs_f16(int *count) {
 }
 
 static const GroupedKernel kGrouped =
-    make_grouped<LpCfg<GEMM_MODE_F16, 128, 128, 32>, LpCfg<GEMM_MODE_F16, 64, 64>, GROUPED_OCC, GROUPED_DEPTH>(13, 6);
+    make_grouped<LpCfg<GEMM_MODE_F16, 128, 128, 32>, LpCfg<GEMM_MODE_F16, 128, 128, 32>, GROUPED_OCC, GROUPED_DEPTH>(
+        13, 13, 13, 6);
 
 const GroupedKernel *lp_grouped_f16() { return &kGrouped; }

@@ -2,7 +2,7 @@
 // (register-staged tiles and asynchronous-copy tiles with 4-byte loads for
 // any shape; asynchronous-copy tiles with 16-byte loads for shapes whose k, n
 // and row strides are whole 16-byte chunks) and the grouped persistent launch
-// (register-staged 128x128 and 64x64 tiles).
+// (register-staged 128x128 tiles; 128x128 or 64x64 for a problem alone).
 #include "kernels_impl.hpp"
 #include "tile_f32.hpp"
 #include "tile_lp2.hpp"
@@ -43,8 +43,8 @@ static const KernelCfg kF32Configs[] = {
     make_cfg<Lp2Cfg<GEMM_MODE_F32, 256, 128, 2, 2, 2, 128>, 1, 4>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F32, 128, 256, 2, 2, 2, 128>, 1, 4>(),
     make_cfg<Lp2Cfg<GEMM_MODE_F32, 128, 128, 2, 2, 2, 128>, 2, 4>(),
-    // register-staged 64 x 64 with k-tiles of 32: the grouped launch's small
-    // tile (16 KB of operands per k-tile, as its 128 x 128 x 16 tile)
+    // register-staged 64 x 64 with k-tiles of 32: the smaller tile of a
+    // grouped problem launched on its own
     make_cfg<F32Cfg<64, 64, 2, 2, 32>, 3>(),
     // asynchronous-copy tiles with 4-byte direct loads (one element per
     // lane): any shape, stride and alignment; four-stage LDS rings of k-tiles
@@ -59,6 +59,6 @@ const KernelCfg *f32_configs(int *count) {
 }
 
 static const GroupedKernel kF32Grouped =
-    make_grouped<F32Cfg<128, 128, 2, 2, 16>, F32Cfg<64, 64, 2, 2, 32>, GROUPED_OCC, GROUPED_DEPTH>(18, 24);
+    make_grouped<F32Cfg<128, 128, 2, 2, 16>, F32Cfg<128, 128, 2, 2, 16>, GROUPED_OCC, GROUPED_DEPTH>(18, 18, 18, 24);
 
 const GroupedKernel *f32_grouped() { return &kF32Grouped; }

@@ -1,7 +1,7 @@
 // F8E4M3 product kernels: the plain launch for every tile configuration
 // (register-staged tiles for any shape; asynchronous-copy tiles for shapes
 // whose k, n and row strides are whole 16-byte chunks) and the grouped
-// persistent launch (128x128 and 64x64 tiles).
+// persistent launch (128x128 tiles; 128x128 or 64x64 for a problem alone).
 #include "kernels_impl.hpp"
 #include "tile_lp.hpp"
 #include "tile_lp2.hpp"
@@ -25,6 +25,7 @@ const KernelCfg *lp_configs_f8(int *count) {
 }
 
 static const GroupedKernel kGrouped =
-    make_grouped<LpCfg<GEMM_MODE_F8E4M3, 128, 128, 64>, LpCfg<GEMM_MODE_F8E4M3, 64, 64>, GROUPED_OCC, GROUPED_DEPTH>(11, 6);
+    make_grouped<LpCfg<GEMM_MODE_F8E4M3, 128, 128, 64>, LpCfg<GEMM_MODE_F8E4M3, 128, 128, 64>, GROUPED_OCC, GROUPED_DEPTH>(
+        11, 11, 11, 6);
 
 const GroupedKernel *lp_grouped_f8() { return &kGrouped; }

@@ -28,7 +28,7 @@ static int grouped_model(int mode, int64_t m, int64_t n, bool alone, double smal
     double best = 1e300;
     int pick = 0;
     for (int c = 0; c < 2; ++c) {
-        const KernelCfg &kc = t[gk->cfg_idx[c]];
+        const KernelCfg &kc = t[alone ? gk->alone_idx[c] : gk->cfg_idx[c]];
         const double tiles = (double)((m + kc.bm - 1) / kc.bm) * (double)((n + kc.bn - 1) / kc.bn);
         const double eff = (kc.bm * kc.bn >= 16384) ? 1.0 : small_eff;
         // alone, rounds of resident workgroups count: a mid-size product on
@@ -471,7 +471,7 @@ int gemm_tune_grouped(int32_t mode, int64_t m, int64_t n, int64_t k, void *strea
         rc = fail(GEMM_EHIP, "filling the tuning operands failed");
     float alone_ms[2] = {0.f, 0.f};
     for (int o = 0; o < 2 && rc == GEMM_OK; ++o)
-        rc = time_median(s, 7, [&] { return enqueue_plain(p, gk->cfg_idx[o], 1, nullptr, s); }, &alone_ms[o]);
+        rc = time_median(s, 7, [&] { return enqueue_plain(p, gk->alone_idx[o], 1, nullptr, s); }, &alone_ms[o]);
     if (rc == GEMM_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(GEMM_EHIP, "stream sync failed");
     (void)hipFree(buf);
     if (rc != GEMM_OK) return rc;
@@ -545,7 +545,7 @@ int gemm_tune_grouped_mix(const gemm_problem_t *ps, int32_t count, void *stream)
     return GEMM_OK;
 }
 
-int gemm_grouped_info(int32_t mode, int32_t info[4]) {
+int gemm_grouped_info(int32_t mode, int32_t info[6]) {
     clear_error();
     if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
     if (!info) return fail(GEMM_EINVAL, "info is NULL");
@@ -555,6 +555,8 @@ int gemm_grouped_info(int32_t mode, int32_t info[4]) {
     info[1] = gk->cfg_idx[1];
     info[2] = gk->wg_per_cu;
     info[3] = gk->lds_bytes;
+    info[4] = gk->alone_idx[0];
+    info[5] = gk->alone_idx[1];
     return GEMM_OK;
 }
 
@@ -568,7 +570,7 @@ int gemm_grouped_lookup(int32_t mode, int64_t m, int64_t n, int64_t k, int32_t o
     int alone = 0;
     const bool measured = tuner_grouped_alone(mode, m, n, k, &alone) && tuner_grouped_eff(mode) > 0;
     out[0] = gk->cfg_idx[grouped_choose(mode, m, n, k)];
-    out[1] = gk->cfg_idx[grouped_choose_alone(mode, m, n, k)];
+    out[1] = gk->alone_idx[grouped_choose_alone(mode, m, n, k)];
     out[2] = measured ? 1 : 0;
     return GEMM_OK;
 }

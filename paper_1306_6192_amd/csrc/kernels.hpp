@@ -44,11 +44,14 @@ struct KernelCfg {
     int presplit;
 };
 
-// The grouped kernel of a mode: two tile configurations (indices into the
-// mode's plain table, so a problem gets the same tiles -- and bits -- as a
-// plain launch of that configuration).
+// The grouped kernel of a mode: the tile configurations its stream runs
+// (indices into the mode's plain table, so a problem gets the same tiles --
+// and bits -- as a plain launch of that configuration; the two are equal
+// when the stream runs one), and the larger and the smaller configuration a
+// problem launched on its own may take (a serving batch of one).
 struct GroupedKernel {
     int cfg_idx[2];
+    int alone_idx[2];
     int wg_per_cu;             // resident workgroups per CU (launch bound and LDS)
     int lds_bytes;             // LDS per workgroup
     GroupedLaunchFn launch;

@@ -22,12 +22,17 @@ __global__ __launch_bounds__(Cfg::THREADS, OCC) void gemm_plain_kernel(TileProbl
 template <int A, int B> struct cmax { static constexpr int v = A > B ? A : B; };
 
 // Grouped launch: resident workgroups per CU and depth of the register ring
-// (k-tiles in flight per workgroup: GROUPED_DEPTH - 1).
+// (k-tiles in flight per workgroup: GROUPED_DEPTH - 1).  Three workgroups of
+// one 128x128 tile with one k-tile in flight each measured faster than two
+// workgroups of two tiles (128x128 and 64x64) with three in flight: the
+// stream is bound by its per-step instructions, which more resident waves
+// overlap, and the larger ring or the second tile's registers do not fit
+// three workgroups.
 #ifndef GROUPED_OCC
-#define GROUPED_OCC 2
+#define GROUPED_OCC 3
 #endif
 #ifndef GROUPED_DEPTH
-#define GROUPED_DEPTH 4
+#define GROUPED_DEPTH 2
 #endif
 
 template <class Cfg, int OCC>
@@ -45,10 +50,12 @@ static hipError_t launch_grouped_t(const GroupedArgs &G, int nwg, hipStream_t s)
 
 // A grouped kernel's table entry: its resident workgroups per CU are the
 // launch bound, capped by what fits in the CU's 160 KiB of LDS (two stages
-// of the larger tile).
+// of the larger tile); alone0 / alone1 are the larger and the smaller plain
+// configuration a problem launched on its own may take.
 template <class Cfg0, class Cfg1, int OCC, int DEPTH>
-constexpr GroupedKernel make_grouped(int cfg0, int cfg1) {
+constexpr GroupedKernel make_grouped(int cfg0, int cfg1, int alone0, int alone1) {
     return GroupedKernel{{cfg0, cfg1},
+                         {alone0, alone1},
                          (160 * 1024 / (2 * GsRing<Cfg0, Cfg1>::STAGE)) < OCC
                              ? (160 * 1024 / (2 * GsRing<Cfg0, Cfg1>::STAGE))
                              : OCC,

@@ -218,7 +218,7 @@ int Server::launch_batch(Slot &s, std::vector<Request *> &b) {
         const gemm_problem_t &p = b[0]->p;
         const GroupedKernel *gk = grouped_kernel(p.mode);
         if (!gk) return fail(GEMM_EUNSUPPORTED, "mode %d has no grouped kernel", p.mode);
-        const int cfg = gk->cfg_idx[grouped_choose_alone(p.mode, p.m, p.n, p.k)];
+        const int cfg = gk->alone_idx[grouped_choose_alone(p.mode, p.m, p.n, p.k)];
         int rc = enqueue_plain(p, cfg, 1, nullptr, s.stream);
         if (rc != GEMM_OK) return rc;
         MG_HIP(hipEventRecord(s.done, s.stream));

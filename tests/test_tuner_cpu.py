@@ -29,7 +29,7 @@ def lookup(mode, m, n, k):
 
 
 def grouped_info(mode):
-    info = (ctypes.c_int32 * 4)()
+    info = (ctypes.c_int32 * 6)()
     _lib.check(_lib.load().gemm_grouped_info(mode, info))
     return list(info)
 
@@ -64,7 +64,7 @@ def test_grouped_occupancy_plan_fits_lds(mode):
     """The planner's resident workgroups per CU times the kernel's LDS fits the
     CU, and (when the build's resource report is present) matches the
     occupancy the compiler reports for that kernel."""
-    cfg0, cfg1, wg_per_cu, lds = grouped_info(mode)
+    cfg0, cfg1, wg_per_cu, lds, alone0, alone1 = grouped_info(mode)
     assert wg_per_cu >= 1
     assert wg_per_cu * lds <= LDS_PER_CU, (mode, wg_per_cu, lds)
     # the kernel's LDS is two stages of the larger tile (the plain
@@ -141,15 +141,15 @@ def test_bucket_entry_serves_unmeasured_shapes(tmp_path):
 
 
 def test_grouped_planner_takes_the_table_choice(tmp_path):
-    """In a batch the planner takes the cost model's tile under the small-tile
-    efficiency the table holds for the mode (a measured "grouped_eff" line);
-    alone it takes the bucket's measured tile.  Both tiles give the same
-    bits, so only the speed depends on these entries."""
+    """In a batch every problem runs on the stream's tile (for a two-tile
+    stream, the cost model's pick under the small-tile efficiency the table
+    holds for the mode); alone it takes the bucket's measured configuration
+    between the two gemm_grouped_info lists.  Every configuration gives the
+    same bits, so only the speed depends on these entries."""
     mode = _lib.MODE_F16
-    cfg0, cfg1, wg_per_cu, _ = grouped_info(mode)
-    small = cfg1 if config_info(mode, cfg1)[0] * config_info(mode, cfg1)[1] < \
-        config_info(mode, cfg0)[0] * config_info(mode, cfg0)[1] else cfg0
-    large = cfg0 + cfg1 - small
+    cfg0, cfg1, wg_per_cu, _, alone0, alone1 = grouped_info(mode)
+    area = lambda c: config_info(mode, c)[0] * config_info(mode, c)[1]
+    assert area(alone1) < area(alone0)
     m, n, k = 3000, 2900, 40000          # k outside every tuned bucket
     before = grouped_lookup(mode, m, n, k)
     assert before[2] == 0
@@ -161,9 +161,15 @@ def test_grouped_planner_takes_the_table_choice(tmp_path):
     empty = prob(mode, 0, 900, 300, A=A_PTR + 6 * (1 << 34), B=B_PTR + 6 * (1 << 34), C=C_PTR + 6 * (1 << 34))
     arr = _lib.problems_array(probs + [other, empty])
     try:
-        # padded area: 2162 small tiles of 64x64 against 552 large of 128x128;
-        # at efficiency 4 the small tile costs a quarter, at 0.05 twenty times
-        for eff, want in ((4.0, small), (0.05, large)):
+        if cfg0 == cfg1:
+            effs = ((4.0, cfg0), (0.05, cfg0))
+        else:
+            # padded area: 2162 small tiles of 64x64 against 552 large of
+            # 128x128; at efficiency 4 the small tile costs a quarter, at
+            # 0.05 twenty times
+            small = cfg1 if area(cfg1) < area(cfg0) else cfg0
+            effs = ((4.0, small), (0.05, cfg0 + cfg1 - small))
+        for eff, want in effs:
             f.write_text('{"grouped_eff": %d, "eff": %.3f}\n' % (mode, eff))
             _lib.check(lib.gemm_tuner_load(str(f).encode()))
             assert grouped_lookup(mode, m, n, k)[0] == want, eff
@@ -172,19 +178,19 @@ def test_grouped_planner_takes_the_table_choice(tmp_path):
             assert list(out[:3]) == [want] * 3, eff
             assert out[3] == grouped_lookup(mode, 700, 900, 300)[0]
             assert out[4] == -1
+        large = effs[1][1]
         # an efficiency outside (0, 4] is not loaded
         f.write_text('{"grouped_eff": %d, "eff": 9.0}\n' % mode)
         _lib.check(lib.gemm_tuner_load(str(f).encode()))
         assert grouped_lookup(mode, m, n, k)[0] == large
-        # alone: the bucket's measured tile, in the current form and in the
-        # older form that also carried an in-batch tile (ignored now)
+        # alone: the bucket's measured configuration, in the current form and
+        # in the older form that also carried an in-batch tile (ignored now)
         for flip, line in ((0, '"alone": %d'), (1, '"tile": 0, "alone": %d'), (0, '"tile": 1, "alone": %d')):
-            alone = (cfg0, cfg1)[flip]
             f.write_text(('{"bucket": "grouped", "mode": %d, "bm": %d, "bn": %d, "bk": %d, ' + line + '}\n')
                          % (mode, bucket(m), bucket(n), bucket(k), flip))
             _lib.check(lib.gemm_tuner_load(str(f).encode()))
             after = grouped_lookup(mode, m, n, k)
-            assert after[1] == alone and after[2] == 1
+            assert after[1] == (alone0, alone1)[flip] and after[2] == 1
             assert after[0] == large
     finally:
         # back to the default efficiency, then the shipped table's entries
@@ -200,7 +206,7 @@ def test_grouped_lookup_and_plan_validate():
     out = (ctypes.c_int32 * 3)()
     assert lib.gemm_grouped_lookup(9, 1, 1, 1, out) == _lib.GEMM_EINVAL
     assert lib.gemm_grouped_lookup(0, -1, 1, 1, out) == _lib.GEMM_EINVAL
-    info = (ctypes.c_int32 * 4)()
+    info = (ctypes.c_int32 * 6)()
     assert lib.gemm_grouped_info(5, info) == _lib.GEMM_EINVAL
     bad = _lib.problems_array([prob(0, 4, 4, 4), prob(1, 4, 4, 4, A=A_PTR + 4096, B=B_PTR + 4096, C=C_PTR + 4096)])
     cfgs = (ctypes.c_int32 * 2)()
