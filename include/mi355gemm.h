@@ -236,22 +236,25 @@ int gemm_errnorm(const float *C, int64_t ldc, const double *R, int64_t ldr,
 /* decomposition (one thread block per output tile, Fig. 5) across         */
 /* problems, with one queue of tiles over all of them.                     */
 
-/* All problems must share one mode (F32 or BF16/F16/F8E4M3/split).  Every
- * problem runs on the grouped kernel's tile (128 x 128; a kernel built with
- * two tiles picks one per problem by the cost model, or the smaller one when
- * the launch would not fill the chip); every tile of a mode gives the same
- * bits, so a problem's result does not depend on the other problems and
- * equals gemm_plain's with split_k = 1.  The host builds a static schedule (gemm_grouped_schedule)
+/* All problems must share one mode (F32 or BF16/F16/F8E4M3/split).  The
+ * mode's grouped kernel is the variant the autotuner measured fastest on a
+ * mixed batch (gemm_tune_grouped_mix; variant 0 when not measured): variant
+ * 0 runs every problem on one 128 x 128 tile, variant 1 on 128 x 128 or
+ * 64 x 64 by the cost model (all on the smaller one when the launch would
+ * not fill the chip).  Every tile of a mode gives the same bits, so a
+ * problem's result does not depend on the other problems or the variant,
+ * and equals gemm_plain's with split_k = 1.  The host builds a static schedule (gemm_grouped_schedule)
  * and uploads it with the descriptors into the (device, stream) pair's
  * workspace, so calls on different streams run independently, and calls on
  * one stream are ordered by it. */
 int gemm_grouped(const gemm_problem_t *ps, int32_t count, void *stream);
 
-/* The grouped kernel of `mode`: info[0..5] = {first and second tile
+/* The grouped kernel of `mode` in use: info[0..6] = {first and second tile
  * configuration of its stream (indices into gemm_config_info; equal when it
  * runs one), resident workgroups per CU, LDS bytes per workgroup, the larger
- * and the smaller configuration a problem launched on its own may take}. */
-int gemm_grouped_info(int32_t mode, int32_t info[6]);
+ * and the smaller configuration a problem launched on its own may take, the
+ * variant (0 or 1)}. */
+int gemm_grouped_info(int32_t mode, int32_t info[7]);
 
 /* The tile configuration a problem of this shape gets in a grouped launch
  * (out[0]: the stream's tile, or for a two-tile stream the cost model's
@@ -310,13 +313,13 @@ int gemm_tune_bucket(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream
  * a serving batch of one gets.  Synchronises.  Dimensions up to 65536.
  * Errors: GEMM_EINVAL, GEMM_EUNSUPPORTED, GEMM_ENOMEM, GEMM_EHIP. */
 int gemm_tune_grouped(int32_t mode, int64_t m, int64_t n, int64_t k, void *stream);
-/* Calibrate, on the caller's mixed problem list (one mode, device operands
- * the caller owns; C is overwritten), the cost model that picks each
- * problem's tile in a grouped launch of a two-tile stream (a one-tile stream
- * has nothing to pick; the default is then recorded): the small tile's efficiency relative
- * to the large one is varied over a grid, each resulting plan is timed
- * (median of seven launches, two passes), and the fastest is recorded for
- * the mode; the default (0.6) is kept unless another is more than 1 %
+/* Choose, on the caller's mixed problem list (one mode, device operands the
+ * caller owns; C is overwritten), the mode's grouped kernel variant and the
+ * cost model that picks each problem's tile in variant 1: variant 0, and
+ * variant 1 with the small tile's efficiency relative to the large one
+ * varied over a grid, are each planned and timed (median of seven launches,
+ * two passes), and the fastest is recorded for the mode; variant 0 (with
+ * the default efficiency 0.6) is kept unless another is more than 1 %
  * faster.  Synchronises.  Errors: as gemm_grouped, plus GEMM_EHIP. */
 int gemm_tune_grouped_mix(const gemm_problem_t *ps, int32_t count, void *stream);
 /* The (cfg, split_k) gemm_plain would use for this shape: the exact entry,

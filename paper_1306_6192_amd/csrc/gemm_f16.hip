@@ -37,8 +37,10 @@ const KernelCfg *lp_configs_f16(int *count) {
     return kTable;
 }
 
-static const GroupedKernel kGrouped =
-    make_grouped<LpCfg<GEMM_MODE_F16, 128, 128, 32>, LpCfg<GEMM_MODE_F16, 128, 128, 32>, GROUPED_OCC, GROUPED_DEPTH>(
-        13, 13, 13, 6);
+static const GroupedKernel kGrouped[2] = {
+    make_grouped<LpCfg<GEMM_MODE_F16, 128, 128, 32>, LpCfg<GEMM_MODE_F16, 128, 128, 32>, GROUPED_ONE_OCC,
+                 GROUPED_ONE_DEPTH>(13, 13, 13, 6),
+    make_grouped<LpCfg<GEMM_MODE_F16, 128, 128, 32>, LpCfg<GEMM_MODE_F16, 64, 64>, GROUPED_TWO_OCC,
+                 GROUPED_TWO_DEPTH>(13, 6, 13, 6)};
 
-const GroupedKernel *lp_grouped_f16() { return &kGrouped; }
+const GroupedKernel *lp_grouped_f16(int variant) { return &kGrouped[variant]; }

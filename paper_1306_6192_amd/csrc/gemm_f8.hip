@@ -24,8 +24,10 @@ const KernelCfg *lp_configs_f8(int *count) {
     return kTable;
 }
 
-static const GroupedKernel kGrouped =
-    make_grouped<LpCfg<GEMM_MODE_F8E4M3, 128, 128, 64>, LpCfg<GEMM_MODE_F8E4M3, 128, 128, 64>, GROUPED_OCC, GROUPED_DEPTH>(
-        11, 11, 11, 6);
+static const GroupedKernel kGrouped[2] = {
+    make_grouped<LpCfg<GEMM_MODE_F8E4M3, 128, 128, 64>, LpCfg<GEMM_MODE_F8E4M3, 128, 128, 64>, GROUPED_ONE_OCC,
+                 GROUPED_ONE_DEPTH>(11, 11, 11, 6),
+    make_grouped<LpCfg<GEMM_MODE_F8E4M3, 128, 128, 64>, LpCfg<GEMM_MODE_F8E4M3, 64, 64>, GROUPED_TWO_OCC,
+                 GROUPED_TWO_DEPTH>(11, 6, 11, 6)};
 
-const GroupedKernel *lp_grouped_f8() { return &kGrouped; }
+const GroupedKernel *lp_grouped_f8(int variant) { return &kGrouped[variant]; }

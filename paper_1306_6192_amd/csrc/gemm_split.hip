@@ -42,17 +42,28 @@ const KernelCfg *lp_configs_split(int *count) {
     return table.data();
 }
 
-// The grouped launch's tile: 128 x 128 with k-tiles of 16 (the last entry
-// of the table above); a problem launched on its own takes it or 64 x 64.
-const GroupedKernel *lp_grouped_split() {
-    static const GroupedKernel k = [] {
-        GroupedKernel g = make_grouped<LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 128, 128, 16>,
-                                       LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 128, 128, 16>, GROUPED_OCC, GROUPED_DEPTH>(
-            0, 0, 0, 5);
-        int n = 0;
-        lp_configs_split(&n);
-        g.cfg_idx[0] = g.cfg_idx[1] = g.alone_idx[0] = n - 1;
-        return g;
-    }();
-    return &k;
+// The grouped launches' tiles: 128 x 128 with k-tiles of 16 (the last entry
+// of the table above) and, in variant 1, 64 x 64; a problem launched on its
+// own takes either.
+const GroupedKernel *lp_grouped_split(int variant) {
+    static const GroupedKernel k[2] = {
+        [] {
+            GroupedKernel g = make_grouped<LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 128, 128, 16>,
+                                           LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 128, 128, 16>, GROUPED_ONE_OCC,
+                                           GROUPED_ONE_DEPTH>(0, 0, 0, 5);
+            int n = 0;
+            lp_configs_split(&n);
+            g.cfg_idx[0] = g.cfg_idx[1] = g.alone_idx[0] = n - 1;
+            return g;
+        }(),
+        [] {
+            GroupedKernel g = make_grouped<LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 128, 128, 16>,
+                                           LpCfg<GEMM_MODE_F32_SPLIT_BF16X3, 64, 64>, GROUPED_TWO_OCC,
+                                           GROUPED_TWO_DEPTH>(0, 5, 0, 5);
+            int n = 0;
+            lp_configs_split(&n);
+            g.cfg_idx[0] = g.alone_idx[0] = n - 1;
+            return g;
+        }()};
+    return &k[variant];
 }

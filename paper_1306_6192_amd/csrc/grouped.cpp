@@ -45,6 +45,7 @@ static int grouped_model(int mode, int64_t m, int64_t n, bool alone, double smal
 
 // Set by gemm_tune_grouped_mix while it plans its candidates.
 static thread_local double t_eff_override = -1.0;
+static thread_local int t_variant_override = -1;
 
 static double small_eff_of(int mode) {
     if (t_eff_override > 0) return t_eff_override;
@@ -70,9 +71,12 @@ int grouped_choose_alone(int mode, int64_t m, int64_t n, int64_t k) {
     return grouped_model(mode, m, n, true, small_eff_of(mode));
 }
 
+// The mode's grouped kernel: the variant the autotuner measured fastest on a
+// mixed batch (gemm_tune_grouped_mix), else variant 0.
 const GroupedKernel *grouped_kernel(int mode) {
-    if (mode == GEMM_MODE_F32) return f32_grouped();
-    return lp_grouped(mode);
+    const int v = t_variant_override >= 0 ? t_variant_override : tuner_grouped_variant(mode);
+    if (mode == GEMM_MODE_F32) return f32_grouped(v);
+    return lp_grouped(mode, v);
 }
 
 // Cost of one output tile in the static schedule, in microseconds of one
@@ -488,34 +492,43 @@ int gemm_tune_grouped_mix(const gemm_problem_t *ps, int32_t count, void *stream)
     if (check.total_tiles == 0) return fail(GEMM_EINVAL, "tuning needs a non-empty product");
     const int mode = check.mode;
     hipStream_t s = (hipStream_t)stream;
-    // candidate efficiencies of the small tile; the model's default is one
-    // of them, and a candidate replaces it only if it is more than 1 % faster
+    // candidates: variant 0 (one tile), and variant 1 (two tiles) under each
+    // candidate small-tile efficiency; the first (variant 0 at the default
+    // efficiency) is kept unless another is more than 1 % faster
     static const double grid[] = {0.3, 0.45, kDefaultSmallEff, 0.75, 0.9, 1.0, 1.25, 1.6};
     const int ng = (int)(sizeof(grid) / sizeof(grid[0]));
-    std::vector<std::vector<GroupDesc>> seen;
-    std::vector<int> plan_of(ng, -1);
+    struct Cand {
+        int variant;
+        double eff;
+    };
+    std::vector<Cand> cands{{0, kDefaultSmallEff}};
+    for (int g = 0; g < ng; ++g) cands.push_back({1, grid[g]});
+    const int nc = (int)cands.size();
+    std::vector<std::pair<int, std::vector<int32_t>>> seen;   // (variant, tile choices)
+    std::vector<int> plan_of(nc, -1);
     std::vector<float> best_ms;
     void *image = nullptr;
     for (int pass = 0; pass < 2 && rc == GEMM_OK; ++pass) {
-        for (int g = 0; g < ng && rc == GEMM_OK; ++g) {
-            t_eff_override = grid[g];
+        for (int c = 0; c < nc && rc == GEMM_OK; ++c) {
+            t_variant_override = cands[c].variant;
+            t_eff_override = cands[c].eff;
             GroupPlan plan;
             rc = build_group_plan(ps, count, plan);
             t_eff_override = -1.0;
+            t_variant_override = -1;
             if (rc != GEMM_OK) break;
-            // candidates that give the same tile choices share one timing
+            // candidates that give the same kernel and tile choices share one timing
+            std::vector<int32_t> choice(plan.descs.size());
+            for (size_t i = 0; i < plan.descs.size(); ++i) choice[i] = plan.descs[i].cfg;
             int id = -1;
-            for (size_t j = 0; j < seen.size(); ++j) {
-                bool same = seen[j].size() == plan.descs.size();
-                for (size_t i = 0; same && i < plan.descs.size(); ++i) same = seen[j][i].cfg == plan.descs[i].cfg;
-                if (same) id = (int)j;
-            }
+            for (size_t j = 0; j < seen.size(); ++j)
+                if (seen[j].first == cands[c].variant && seen[j].second == choice) id = (int)j;
             if (id < 0) {
                 id = (int)seen.size();
-                seen.push_back(plan.descs);
+                seen.emplace_back(cands[c].variant, choice);
                 best_ms.push_back(1e30f);
             }
-            plan_of[g] = id;
+            plan_of[c] = id;
             const size_t bytes = plan_image_bytes(plan);
             std::vector<uint8_t> host(bytes);
             plan_image_write(plan, host.data());
@@ -533,19 +546,18 @@ int gemm_tune_grouped_mix(const gemm_problem_t *ps, int32_t count, void *stream)
         }
     }
     t_eff_override = -1.0;
+    t_variant_override = -1;
     if (rc == GEMM_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(GEMM_EHIP, "stream sync failed");
     if (image) (void)hipFree(image);
     if (rc != GEMM_OK) return rc;
-    int def = 0;
-    while (def < ng && grid[def] != kDefaultSmallEff) ++def;
-    int pick = def;
-    for (int g = 0; g < ng; ++g)
-        if (best_ms[plan_of[g]] < 0.99f * best_ms[plan_of[pick]]) pick = g;
-    tuner_record_grouped_eff(mode, grid[pick]);
+    int pick = 0;
+    for (int c = 1; c < nc; ++c)
+        if (best_ms[plan_of[c]] < 0.99f * best_ms[plan_of[pick]]) pick = c;
+    tuner_record_grouped_eff(mode, cands[pick].eff, cands[pick].variant);
     return GEMM_OK;
 }
 
-int gemm_grouped_info(int32_t mode, int32_t info[6]) {
+int gemm_grouped_info(int32_t mode, int32_t info[7]) {
     clear_error();
     if (!mode_known(mode)) return fail(GEMM_EINVAL, "unknown mode %d", mode);
     if (!info) return fail(GEMM_EINVAL, "info is NULL");
@@ -557,6 +569,7 @@ int gemm_grouped_info(int32_t mode, int32_t info[6]) {
     info[3] = gk->lds_bytes;
     info[4] = gk->alone_idx[0];
     info[5] = gk->alone_idx[1];
+    info[6] = t_variant_override >= 0 ? t_variant_override : tuner_grouped_variant(mode);
     return GEMM_OK;
 }
 

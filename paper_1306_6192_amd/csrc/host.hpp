@@ -68,15 +68,18 @@ void heuristic_choose(int mode, int64_t m, int64_t n, int64_t k, int *cfg, int *
 // floor(log2(d)) (0 for d <= 1): the bucket of a dimension in the tables.
 int dim_bucket(int64_t d);
 // The grouped table's tile option for a problem launched alone (0 or 1: the
-// grouped kernel's first or second configuration) for the bucket of
-// (m, n, k); false when the bucket has not been measured.
+// larger or the smaller of the grouped kernel's alone configurations) for
+// the bucket of (m, n, k); false when the bucket has not been measured.
 bool tuner_grouped_alone(int mode, int64_t m, int64_t n, int64_t k, int *alone);
 void tuner_record_grouped(int mode, int64_t m, int64_t n, int64_t k, int alone);
-// The measured efficiency of the grouped kernel's small tile relative to its
-// large one in a mixed batch (the planner's cost model weighs the padded
-// tile area by it); < 0 when not measured.
+// The measured efficiency of a two-tile grouped kernel's small tile relative
+// to its large one in a mixed batch (the planner's cost model weighs the
+// padded tile area by it); < 0 when not measured.
 double tuner_grouped_eff(int mode);
-void tuner_record_grouped_eff(int mode, double eff);
+// The grouped kernel variant measured fastest on a mixed batch (0 when not
+// measured); recorded together with the efficiency.
+int tuner_grouped_variant(int mode);
+void tuner_record_grouped_eff(int mode, double eff, int variant);
 
 // A device buffer owned by the library that grows on demand.  Growth waits
 // for `s` to drain before freeing the old allocation.

@@ -63,8 +63,9 @@ const KernelCfg *f32_configs(int *count);
 const KernelCfg *lp_configs(int mode, int *count);
 const KernelCfg *f64_configs(int *count);   // binary64 (plain launches only)
 const KernelCfg *c32_configs(int *count);   // complex float (plain launches only)
-const GroupedKernel *f32_grouped();
-const GroupedKernel *lp_grouped(int mode);
+// Grouped kernel `variant` (0 or 1, see kernels_impl.hpp) of a mode.
+const GroupedKernel *f32_grouped(int variant);
+const GroupedKernel *lp_grouped(int mode, int variant);
 
 // Elementwise / reduction kernels (misc.hip).
 hipError_t launch_fill_zero(float *C, int64_t ldc, int m, int n, hipStream_t s);

@@ -21,19 +21,17 @@ __global__ __launch_bounds__(Cfg::THREADS, OCC) void gemm_plain_kernel(TileProbl
 
 template <int A, int B> struct cmax { static constexpr int v = A > B ? A : B; };
 
-// Grouped launch: resident workgroups per CU and depth of the register ring
-// (k-tiles in flight per workgroup: GROUPED_DEPTH - 1).  Three workgroups of
-// one 128x128 tile with one k-tile in flight each measured faster than two
-// workgroups of two tiles (128x128 and 64x64) with three in flight: the
-// stream is bound by its per-step instructions, which more resident waves
-// overlap, and the larger ring or the second tile's registers do not fit
-// three workgroups.
-#ifndef GROUPED_OCC
-#define GROUPED_OCC 3
-#endif
-#ifndef GROUPED_DEPTH
-#define GROUPED_DEPTH 2
-#endif
+// The two grouped kernels of a mode (the autotuner picks one per mode on a
+// mixed batch; variant 0 unless measured otherwise): resident workgroups per
+// CU and depth of the register ring (k-tiles in flight: DEPTH - 1).
+//   0: one 128x128 tile, three workgroups per CU, one k-tile in flight;
+//   1: two tiles (128x128 and 64x64, the cost model choosing per problem),
+//      two workgroups per CU, three k-tiles in flight.
+// On the 512-problem workload variant 0 measured faster: the stream is bound
+// by its per-step instructions, which more resident waves overlap, and the
+// second tile's registers or a deeper ring do not fit three workgroups.
+constexpr int GROUPED_ONE_OCC = 3, GROUPED_ONE_DEPTH = 2;
+constexpr int GROUPED_TWO_OCC = 2, GROUPED_TWO_DEPTH = 4;
 
 template <class Cfg, int OCC>
 static hipError_t launch_plain_t(const TileProblem &P, int nwg, hipStream_t s) {

@@ -29,6 +29,7 @@ static std::map<Key, std::pair<int, int>> g_table;          // exact shape -> (c
 static std::map<BKey, std::pair<int, int>> g_plain_bucket;  // bucket -> (cfg, split)
 static std::map<BKey, int> g_grouped;                       // bucket -> option alone
 static double g_grouped_eff[GEMM_NUM_MODES] = {-1, -1, -1, -1, -1};   // small-tile efficiency (< 0: unset)
+static int g_grouped_variant[GEMM_NUM_MODES] = {-1, -1, -1, -1, -1};  // grouped kernel variant (< 0: unset)
 static bool g_env_loaded = false;
 
 int dim_bucket(int64_t d) {
@@ -152,9 +153,17 @@ double tuner_grouped_eff(int mode) {
     return mode_known(mode) ? g_grouped_eff[mode] : -1.0;
 }
 
-void tuner_record_grouped_eff(int mode, double eff) {
+void tuner_record_grouped_eff(int mode, double eff, int variant) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (mode_known(mode)) g_grouped_eff[mode] = eff;
+    if (!mode_known(mode)) return;
+    g_grouped_eff[mode] = eff;
+    g_grouped_variant[mode] = variant;
+}
+
+int tuner_grouped_variant(int mode) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_env_locked();
+    return mode_known(mode) && g_grouped_variant[mode] >= 0 ? g_grouped_variant[mode] : 0;
 }
 
 // One JSON object per line, in one of four forms (the forms gemm_tuner_save
@@ -162,7 +171,7 @@ void tuner_record_grouped_eff(int mode, double eff) {
 //   {"mode": M, "m": m, "n": n, "k": k, "cfg": C, "split": S}
 //   {"bucket": "plain", "mode": M, "bm": a, "bn": b, "bk": c, "cfg": C, "split": S}
 //   {"bucket": "grouped", "mode": M, "bm": a, "bn": b, "bk": c, "alone": U}
-//   {"grouped_eff": M, "eff": E}
+//   {"grouped_eff": M, "eff": E, "variant": V}  (", variant" optional: 0)
 static int load_file_locked(const char *path) {
     FILE *f = fopen(path, "r");
     if (!f) return fail(GEMM_ENOTFOUND, "cannot open tuning file %s", path);
@@ -205,9 +214,12 @@ static int load_file_locked(const char *path) {
             ++n_ok;
         } else {
             double eff = 0;
-            if (sscanf(line, " {\"grouped_eff\": %d, \"eff\": %lf", &mode, &eff) == 2 && mode_known(mode) &&
-                eff > 0 && eff <= 4) {
+            int variant = 0;
+            const int got = sscanf(line, " {\"grouped_eff\": %d, \"eff\": %lf, \"variant\": %d", &mode, &eff,
+                                   &variant);
+            if (got >= 2 && mode_known(mode) && eff > 0 && eff <= 4 && variant >= 0 && variant <= 1) {
                 g_grouped_eff[mode] = eff;
+                g_grouped_variant[mode] = got == 3 ? variant : 0;
                 ++n_ok;
             }
         }
@@ -287,7 +299,9 @@ int gemm_tuner_save(const char *path) {
                 std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
                 kv.second);
     for (int m = 0; m < GEMM_NUM_MODES; ++m)
-        if (g_grouped_eff[m] > 0) fprintf(f, "{\"grouped_eff\": %d, \"eff\": %.3f}\n", m, g_grouped_eff[m]);
+        if (g_grouped_eff[m] > 0)
+            fprintf(f, "{\"grouped_eff\": %d, \"eff\": %.3f, \"variant\": %d}\n", m, g_grouped_eff[m],
+                    std::max(0, g_grouped_variant[m]));
     fclose(f);
     return GEMM_OK;
 }

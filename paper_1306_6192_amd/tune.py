@@ -12,10 +12,11 @@ Three kinds of entries (each chosen by the library's own timing):
 * ``plain-buckets``: the same measurement on one representative shape per
   log2 bucket of (m, n, k) (``gemm_tune_bucket``), consulted for every shape
   without an exact entry;
-* ``grouped``: the grouped kernel's tile per bucket for a problem launched
-  alone (``gemm_tune_grouped``), and the small-tile efficiency of the cost
-  model that picks tiles in a batch, calibrated on a mixed batch of seeded
-  synthetic problems (``gemm_tune_grouped_mix``): 512 problems with m, n, k
+* ``grouped``: the plain tile (128x128 or 64x64) per bucket for a problem
+  launched alone (``gemm_tune_grouped``), and per mode the grouped kernel
+  variant (one tile at three workgroups per CU, or two tiles with a cost
+  model) and the small-tile efficiency of that cost model, measured on a
+  mixed batch of seeded synthetic problems (``gemm_tune_grouped_mix``): 512 problems with m, n, k
   log-uniform in [32, 1024] (the grouped workload's distribution, another
   seed) for FP32, BF16, F16 and split-BF16x3, and 48 problems with m, n, k
   log-uniform in [64, 4096] (a serving batch) for E4M3.
@@ -138,7 +139,7 @@ def main(argv=None):
             if mode not in keep:
                 continue
             calibrate_mix(mg, _lib, lib, torch, mode, count, lo, hi, stream)
-            print(f"grouped mix {mg.MODE_NAMES[mode]}: small-tile efficiency calibrated", flush=True)
+            print(f"grouped mix {mg.MODE_NAMES[mode]}: kernel variant and small-tile efficiency measured", flush=True)
         save()
     buckets = bucket_shapes(mg)
     for kind, entry in (("plain-buckets", lib.gemm_tune_bucket), ("grouped", lib.gemm_tune_grouped)):

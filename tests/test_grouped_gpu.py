@@ -144,3 +144,46 @@ def test_problem_batch_repeated_launches():
         batch.run()
         for i, (_, _, c) in enumerate(ops):
             assert np.array_equal(host(c), want[i]), (rep, i)
+
+
+@pytest.mark.parametrize("mode", [mg.MODE_F32, mg.MODE_BF16, mg.MODE_F8E4M3])
+def test_grouped_variant1_matches_plain_bitwise(mode, tmp_path):
+    """The two-tile grouped kernel (variant 1, selected through the tuning
+    table) gives the same bits as the plain launch too, on the grouped
+    workload (FP32, BF16) or a mixed E4M3 batch."""
+    import os
+    log(f"grouped variant 1 {mg.MODE_NAMES[mode]}")
+    lib = _lib.load()
+    f = tmp_path / "v.jsonl"
+    f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 1}\n' % mode)
+    _lib.check(lib.gemm_tuner_load(str(f).encode()))
+    try:
+        info = (ctypes.c_int32 * 7)()
+        _lib.check(lib.gemm_grouped_info(mode, info))
+        assert info[6] == 1 and info[0] != info[1]
+        if mode == mg.MODE_F8E4M3:
+            probs = synth.grouped_problems(200, 16, 1024, seed=11)
+            ops = []
+            for A, B in probs:
+                qa, sa = mg.quantize_e4m3(dev(A))
+                qb, sb = mg.quantize_e4m3(dev(B))
+                ops.append((qa, qb, torch.empty((A.shape[0], B.shape[1]), device="cuda"),
+                            float(host(sa)[0]), float(host(sb)[0])))
+        else:
+            probs, ops = _group(512, 32, 1024, 0, mode)
+        cfgs = (ctypes.c_int32 * len(ops))()
+        arr = _lib.problems_array([mg.make_problem(t[0], t[1], t[2], mode, *t[3:]) for t in ops])
+        _lib.check(lib.gemm_grouped_plan(arr, len(ops), cfgs))
+        assert {info[0], info[1]} <= set(cfgs) | {-1}, "both tiles are used"
+        mg.grouped(ops, mode=mode)
+        for i, t in enumerate(ops):
+            extra = dict(scale_a=t[3], scale_b=t[4]) if len(t) == 5 else {}
+            ref = host(mg.gemm(t[0], t[1], mode=mode, cfg=3, split_k=1, **extra))
+            assert np.array_equal(host(t[2]), ref), f"problem {i}"
+    finally:
+        f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 0}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(f).encode()))
+        shipped = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                               "paper_1306_6192_amd", "tuning", "mi355x.jsonl")
+        if os.path.exists(shipped):
+            _lib.check(lib.gemm_tuner_load(shipped.encode()))

@@ -29,7 +29,7 @@ def lookup(mode, m, n, k):
 
 
 def grouped_info(mode):
-    info = (ctypes.c_int32 * 6)()
+    info = (ctypes.c_int32 * 7)()
     _lib.check(_lib.load().gemm_grouped_info(mode, info))
     return list(info)
 
@@ -64,7 +64,7 @@ def test_grouped_occupancy_plan_fits_lds(mode):
     """The planner's resident workgroups per CU times the kernel's LDS fits the
     CU, and (when the build's resource report is present) matches the
     occupancy the compiler reports for that kernel."""
-    cfg0, cfg1, wg_per_cu, lds, alone0, alone1 = grouped_info(mode)
+    cfg0, cfg1, wg_per_cu, lds, alone0, alone1, variant = grouped_info(mode)
     assert wg_per_cu >= 1
     assert wg_per_cu * lds <= LDS_PER_CU, (mode, wg_per_cu, lds)
     # the kernel's LDS is two stages of the larger tile (the plain
@@ -77,6 +77,11 @@ def test_grouped_occupancy_plan_fits_lds(mode):
             if not line.startswith("_Z26gemm_grouped_stream_kernel"):
                 continue
             name = line.split()[0]
+            # the kernel's occupancy bound and ring depth are its last two
+            # template arguments: (3, 2) for variant 0, (2, 4) for variant 1
+            tail = re.search(r"Li(\d+)ELi(\d+)EEvPK9GroupDesc", name)
+            if not tail or (int(tail.group(1)), int(tail.group(2))) != ((3, 2), (2, 4))[variant]:
+                continue
             lds_m = re.search(r"LDS Size \[bytes/block\]=(\d+)", line)
             occ_m = re.search(r"Occupancy \[waves/SIMD\]=(\d+)", line)
             if not (lds_m and occ_m) or int(lds_m.group(1)) != lds:
@@ -147,7 +152,7 @@ def test_grouped_planner_takes_the_table_choice(tmp_path):
     between the two gemm_grouped_info lists.  Every configuration gives the
     same bits, so only the speed depends on these entries."""
     mode = _lib.MODE_F16
-    cfg0, cfg1, wg_per_cu, _, alone0, alone1 = grouped_info(mode)
+    cfg0, cfg1, wg_per_cu, _, alone0, alone1, _ = grouped_info(mode)
     area = lambda c: config_info(mode, c)[0] * config_info(mode, c)[1]
     assert area(alone1) < area(alone0)
     m, n, k = 3000, 2900, 40000          # k outside every tuned bucket
@@ -194,7 +199,7 @@ def test_grouped_planner_takes_the_table_choice(tmp_path):
             assert after[0] == large
     finally:
         # back to the default efficiency, then the shipped table's entries
-        f.write_text('{"grouped_eff": %d, "eff": 0.600}\n' % mode)
+        f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 0}\n' % mode)
         _lib.check(lib.gemm_tuner_load(str(f).encode()))
         shipped = os.path.join(ROOT, "paper_1306_6192_amd", "tuning", "mi355x.jsonl")
         if os.path.exists(shipped):
@@ -206,7 +211,7 @@ def test_grouped_lookup_and_plan_validate():
     out = (ctypes.c_int32 * 3)()
     assert lib.gemm_grouped_lookup(9, 1, 1, 1, out) == _lib.GEMM_EINVAL
     assert lib.gemm_grouped_lookup(0, -1, 1, 1, out) == _lib.GEMM_EINVAL
-    info = (ctypes.c_int32 * 6)()
+    info = (ctypes.c_int32 * 7)()
     assert lib.gemm_grouped_info(5, info) == _lib.GEMM_EINVAL
     bad = _lib.problems_array([prob(0, 4, 4, 4), prob(1, 4, 4, 4, A=A_PTR + 4096, B=B_PTR + 4096, C=C_PTR + 4096)])
     cfgs = (ctypes.c_int32 * 2)()
@@ -214,3 +219,40 @@ def test_grouped_lookup_and_plan_validate():
     assert "one mode" in _lib.last_error()
     assert lib.gemm_tune_grouped(0, 0, 4, 4, None) == _lib.GEMM_EINVAL
     assert lib.gemm_tune_bucket(9, 4, 4, 4, None) == _lib.GEMM_EINVAL
+
+
+@pytest.mark.parametrize("mode", [_lib.MODE_F32, _lib.MODE_BF16, _lib.MODE_F8E4M3])
+def test_grouped_variant_from_the_table(mode, tmp_path):
+    """A "variant" in the mode's grouped_eff line selects the grouped kernel:
+    variant 1 runs two tiles (a 128x128 and a 64x64 configuration, two
+    workgroups per CU) and its cost model gives small problems the small
+    tile; variant 0 runs one 128x128 tile at three per CU.  A line without a
+    variant means variant 0."""
+    lib = _lib.load()
+    f = tmp_path / "v.jsonl"
+    shapes = [(32, 40, 64), (900, 1000, 300), (100, 80, 500)]
+    probs = [prob(mode, m, n, k, A=A_PTR + i * (1 << 34), B=B_PTR + i * (1 << 34), C=C_PTR + i * (1 << 34))
+             for i, (m, n, k) in enumerate(shapes * 200)]
+    arr = _lib.problems_array(probs)
+    try:
+        f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 1}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(f).encode()))
+        cfg0, cfg1, wg, lds, a0, a1, v = grouped_info(mode)
+        assert v == 1 and cfg0 != cfg1 and wg == 2 and wg * lds <= LDS_PER_CU
+        assert config_info(mode, cfg0)[:2] == [128, 128] and config_info(mode, cfg1)[:2] == [64, 64]
+        out = (ctypes.c_int32 * len(probs))()
+        _lib.check(lib.gemm_grouped_plan(arr, len(probs), out))
+        assert out[0] == cfg1 and out[1] == cfg0      # the 32x40 problem on 64x64, 900x1000 on 128x128
+        f.write_text('{"grouped_eff": %d, "eff": 0.600}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(f).encode()))
+        cfg0, cfg1, wg, lds, a0, a1, v = grouped_info(mode)
+        assert v == 0 and cfg0 == cfg1 and wg == 3 and wg * lds <= LDS_PER_CU
+        assert config_info(mode, cfg0)[:2] == [128, 128]
+        _lib.check(lib.gemm_grouped_plan(arr, len(probs), out))
+        assert set(out) == {cfg0}
+    finally:
+        f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 0}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(f).encode()))
+        shipped = os.path.join(ROOT, "paper_1306_6192_amd", "tuning", "mi355x.jsonl")
+        if os.path.exists(shipped):
+            _lib.check(lib.gemm_tuner_load(shipped.encode()))
