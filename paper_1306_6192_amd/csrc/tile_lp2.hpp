@@ -367,8 +367,10 @@ __device__ __forceinline__ void lp2_read_piece(const uint8_t *stage, int kc, int
             const int rb = p;
             const int r = wm * Cfg::TM + rb * 32 + l32;
             const uint8_t *row = As + r * Cfg::A_ROWB;
-            const u32x4 lo = *reinterpret_cast<const u32x4 *>(row + 16 * ((2 * g) ^ Cfg::a_swz(r)));
-            const u32x4 hi = *reinterpret_cast<const u32x4 *>(row + 16 * ((2 * g + 1) ^ Cfg::a_swz(r)));
+            // step kc covers chunks 4 kc .. 4 kc + 3 of the row (64 k; one
+            // step per k-tile with 64-byte rows, two with 128-byte rows)
+            const u32x4 lo = *reinterpret_cast<const u32x4 *>(row + 16 * ((4 * kc + 2 * g) ^ Cfg::a_swz(r)));
+            const u32x4 hi = *reinterpret_cast<const u32x4 *>(row + 16 * ((4 * kc + 2 * g + 1) ^ Cfg::a_swz(r)));
             F.a[rb] = (i32x8){(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
                               (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
         } else {
@@ -377,7 +379,7 @@ __device__ __forceinline__ void lp2_read_piece(const uint8_t *stage, int kc, int
             i32x2 q[4];
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
-                const int k = 32 * (G >> 1) + 8 * h + (p16 >> 1);
+                const int k = 64 * kc + 32 * (G >> 1) + 8 * h + (p16 >> 1);
                 const uint8_t *a = Bs + k * Cfg::B_ROWB + 16 * ((n >> 4) ^ Cfg::b_swz(k)) + (n & 15);
                 q[h] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) i32x2 *)a);
             }
