@@ -170,6 +170,9 @@ __device__ __forceinline__ u32x4 gs_ld16_masked(gs_gu8 *base, int64_t ld, int r,
 // The accumulators of one tile to C (the element mapping of tile_epilogue:
 // lane l%32 of block cb holds output column CB*(l%32) + cb of the wave's
 // columns; register r of the 32x32 block holds row 8(r/4) + 4(l/32) + r%4).
+// Each lane's row pointer is computed once; the rows it stores are a fixed
+// offset times ldc from it (scalar arithmetic).  An interior tile stores
+// without any bound test.
 template <class Cfg>
 __device__ __forceinline__ void gs_epilogue(gs_gf32 *C, int64_t ldc, int M, int N, int m0, int n0, float scale,
                                             const f32x16 (&acc)[Cfg::RB][Cfg::CB]) {
@@ -178,14 +181,28 @@ __device__ __forceinline__ void gs_epilogue(gs_gf32 *C, int64_t ldc, int M, int 
     const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
     const int l32 = lane & 31, g = lane >> 5;
     const int col = n0 + wn * Cfg::TN + Cfg::CB * l32;
+    const int row0 = m0 + wm * Cfg::TM + 4 * g;
+    gs_gf32 *base = C + (int64_t)row0 * ldc + col;
+    if (m0 + Cfg::BM <= M && n0 + Cfg::BN <= N) {
+#pragma unroll
+        for (int rb = 0; rb < Cfg::RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                gs_gf32 *p = base + (int64_t)(rb * 32 + 8 * (r >> 2) + (r & 3)) * ldc;
+#pragma unroll
+                for (int cb = 0; cb < Cfg::CB; ++cb) p[cb] = acc[rb][cb][r] * scale;
+            }
+        return;
+    }
+    const int rows_left = M - row0;
     const bool full_cols = col + Cfg::CB <= N;
 #pragma unroll
     for (int rb = 0; rb < Cfg::RB; ++rb) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int row = m0 + wm * Cfg::TM + rb * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-            if (row >= M) continue;
-            gs_gf32 *p = C + (int64_t)row * ldc + col;
+            const int d = rb * 32 + 8 * (r >> 2) + (r & 3);
+            if (d >= rows_left) continue;
+            gs_gf32 *p = base + (int64_t)d * ldc;
             if (full_cols) {
 #pragma unroll
                 for (int cb = 0; cb < Cfg::CB; ++cb) p[cb] = acc[rb][cb][r] * scale;
@@ -389,16 +406,18 @@ __device__ __forceinline__ void gs_advance_cfg(const GsTile &T, gs_gu8 *(&src)[N
 // values across branches, which would make the compiler copy -- and so wait
 // for -- a set still in flight) and one vmcnt count retires the oldest set.
 // Past the end of the list, and for tiny tiles (loaded element-wise when
-// they reach the LDS), the loads read a valid dummy address.  The addresses
-// are computed in full at a tile's first and last k-tile and advanced by
-// one k-tile in between.
+// they reach the LDS), the loads read a valid dummy address (the schedule's
+// first entry).  The addresses are computed in full at a tile's first and
+// last k-tile and advanced by one k-tile in between.
 template <class C0, class C1, int NV>
 __device__ __forceinline__ void gs_lookahead(const GroupDesc *__restrict__ descs,
                                              const GroupTile *__restrict__ tiles, int last, GsState<NV> &s,
                                              u32x4 (&v)[NV]) {
     typedef GsRing<C0, C1> R;
     const bool real = s.li < last;
-    if (real) {
+    // s.src holds the dummy address for a tiny tile and past the end of the
+    // list (set when the cursor gets there), so the loads need no select
+    if (real && !s.LT.tiny) {
         const bool first_cfg = R::ONE || s.LT.cfg == 0;
         if (s.lkt == 0 || s.lkt + 1 == s.LT.nkt) {
             if (first_cfg) gs_addr_cfg<C0>(s.LT, s.lkt, s.src);
@@ -408,13 +427,15 @@ __device__ __forceinline__ void gs_lookahead(const GroupDesc *__restrict__ descs
             else gs_advance_cfg<C1>(s.LT, s.src);
         }
     }
-    const bool use = real && !s.LT.tiny;
-    gs_gu8 *dummy = (gs_gu8 *)tiles;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = gs_ld16(use ? s.src[q] : dummy);
+    for (int q = 0; q < NV; ++q) v[q] = gs_ld16(s.src[q]);
     if (real && ++s.lkt == s.LT.nkt) {
         s.lkt = 0;
         if (++s.li < last) s.LT = gs_tile<R::ESZ>(descs, tiles, s.li);
+        if (s.li >= last || s.LT.tiny) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) s.src[q] = (gs_gu8 *)tiles;
+        }
     }
 }
 
@@ -530,6 +551,8 @@ __global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_grouped_stream_kernel(
     s.lkt = s.ckt = s.step = 0;
     s.LT = gs_tile<R::ESZ>(descs, tiles, first);
     s.CT = gs_cur<R::ESZ>(descs, tiles, first);
+    // the dummy address until the lookahead computes the first tile's
+    // addresses (and for good if that tile is tiny)
 #pragma unroll
     for (int q = 0; q < R::NV; ++q) s.src[q] = (gs_gu8 *)tiles;
     // prologue: k-tiles 0 .. DEPTH-2 of the stream in flight, k-tile 0 in LDS
