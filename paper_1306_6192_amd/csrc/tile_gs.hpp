@@ -530,20 +530,28 @@ __global__ __launch_bounds__(GEMM_THREADS, OCC) void gemm_grouped_stream_kernel(
     const int first = wg_first[blockIdx.x], last = wg_first[blockIdx.x + 1];
     if (first >= last) return;
 
+    // C1's accumulators are C0's first block when C1 has one block per wave
+    // (the two tiles never run at once, and each leaves its accumulators at
+    // zero for the next tile): sixteen registers fewer
     typename GsOps<C0>::Acc acc0;
-    typename GsOps<C1>::Acc acc1;
+    constexpr bool SHARE = !R::ONE && C1::RB == 1 && C1::CB == 1;
+    typename GsOps<C1>::Acc acc1_own;
+    typename GsOps<C1>::Acc &acc1 =
+        SHARE ? *reinterpret_cast<typename GsOps<C1>::Acc *>(&acc0[0][0]) : acc1_own;
 #pragma unroll
     for (int rb = 0; rb < C0::RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < C0::CB; ++cb)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc0[rb][cb][r] = 0.f;
+    if constexpr (!SHARE) {
 #pragma unroll
-    for (int rb = 0; rb < C1::RB; ++rb)
+        for (int rb = 0; rb < C1::RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < C1::CB; ++cb)
+            for (int cb = 0; cb < C1::CB; ++cb)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc1[rb][cb][r] = 0.f;
+                for (int r = 0; r < 16; ++r) acc1[rb][cb][r] = 0.f;
+    }
 
     u32x4 ring[DEPTH][R::NV];
     GsState<R::NV> s;

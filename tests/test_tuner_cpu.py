@@ -224,9 +224,9 @@ def test_grouped_lookup_and_plan_validate():
 @pytest.mark.parametrize("mode", [_lib.MODE_F32, _lib.MODE_BF16, _lib.MODE_F8E4M3])
 def test_grouped_variant_from_the_table(mode, tmp_path):
     """A "variant" in the mode's grouped_eff line selects the grouped kernel:
-    variant 1 runs two tiles (a 128x128 and a 64x64 configuration, two
-    workgroups per CU) and its cost model gives small problems the small
-    tile; variant 0 runs one 128x128 tile at three per CU.  A line without a
+    variant 1 runs two tiles (a 128x128 and a 64x64 configuration, two or
+    three workgroups per CU) and its cost model gives small problems the
+    small tile; variant 0 runs one 128x128 tile at three per CU.  A line without a
     variant means variant 0."""
     lib = _lib.load()
     f = tmp_path / "v.jsonl"
@@ -238,7 +238,7 @@ def test_grouped_variant_from_the_table(mode, tmp_path):
         f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 1}\n' % mode)
         _lib.check(lib.gemm_tuner_load(str(f).encode()))
         cfg0, cfg1, wg, lds, a0, a1, v = grouped_info(mode)
-        assert v == 1 and cfg0 != cfg1 and wg == 2 and wg * lds <= LDS_PER_CU
+        assert v == 1 and cfg0 != cfg1 and wg >= 2 and wg * lds <= LDS_PER_CU
         assert config_info(mode, cfg0)[:2] == [128, 128] and config_info(mode, cfg1)[:2] == [64, 64]
         out = (ctypes.c_int32 * len(probs))()
         _lib.check(lib.gemm_grouped_plan(arr, len(probs), out))
