@@ -256,3 +256,28 @@ def test_grouped_variant_from_the_table(mode, tmp_path):
         shipped = os.path.join(ROOT, "paper_1306_6192_amd", "tuning", "mi355x.jsonl")
         if os.path.exists(shipped):
             _lib.check(lib.gemm_tuner_load(shipped.encode()))
+
+
+def test_grouped_variant_survives_save_and_load(tmp_path):
+    """gemm_tuner_save writes the mode's grouped variant and efficiency, and
+    loading the saved table restores them (the form tune.py ships)."""
+    lib = _lib.load()
+    mode = _lib.MODE_F16
+    f, g = tmp_path / "in.jsonl", tmp_path / "out.jsonl"
+    try:
+        f.write_text('{"grouped_eff": %d, "eff": 0.900, "variant": 1}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(f).encode()))
+        _lib.check(lib.gemm_tuner_save(str(g).encode()))
+        lines = [ln for ln in g.read_text().splitlines() if ln.startswith('{"grouped_eff": %d,' % mode)]
+        assert lines == ['{"grouped_eff": %d, "eff": 0.900, "variant": 1}' % mode]
+        f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 0}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(f).encode()))
+        assert grouped_info(mode)[6] == 0
+        _lib.check(lib.gemm_tuner_load(str(g).encode()))
+        assert grouped_info(mode)[6] == 1
+    finally:
+        f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 0}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(f).encode()))
+        shipped = os.path.join(ROOT, "paper_1306_6192_amd", "tuning", "mi355x.jsonl")
+        if os.path.exists(shipped):
+            _lib.check(lib.gemm_tuner_load(shipped.encode()))
