@@ -146,11 +146,11 @@ def test_problem_batch_repeated_launches():
             assert np.array_equal(host(c), want[i]), (rep, i)
 
 
-@pytest.mark.parametrize("mode", [mg.MODE_F32, mg.MODE_BF16, mg.MODE_F8E4M3])
+@pytest.mark.parametrize("mode", [mg.MODE_F32, mg.MODE_BF16, mg.MODE_F16, mg.MODE_F8E4M3, mg.MODE_SPLIT_BF16X3])
 def test_grouped_variant1_matches_plain_bitwise(mode, tmp_path):
     """The two-tile grouped kernel (variant 1, selected through the tuning
     table) gives the same bits as the plain launch too, on the grouped
-    workload (FP32, BF16) or a mixed E4M3 batch."""
+    workload (FP32, BF16, F16) or a mixed batch (E4M3, split-BF16x3)."""
     import os
     log(f"grouped variant 1 {mg.MODE_NAMES[mode]}")
     lib = _lib.load()
@@ -169,6 +169,9 @@ def test_grouped_variant1_matches_plain_bitwise(mode, tmp_path):
                 qb, sb = mg.quantize_e4m3(dev(B))
                 ops.append((qa, qb, torch.empty((A.shape[0], B.shape[1]), device="cuda"),
                             float(host(sa)[0]), float(host(sb)[0])))
+        elif mode == mg.MODE_SPLIT_BF16X3:
+            probs = synth.grouped_problems(200, 16, 1024, seed=12)
+            ops = [(dev(A), dev(B), torch.empty((A.shape[0], B.shape[1]), device="cuda")) for A, B in probs]
         else:
             probs, ops = _group(512, 32, 1024, 0, mode)
         cfgs = (ctypes.c_int32 * len(ops))()
