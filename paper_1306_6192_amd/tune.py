@@ -86,6 +86,11 @@ def calibrate_mix(mg, _lib, lib, torch, mode, count, lo, hi, stream):
     """gemm_tune_grouped_mix on `count` seeded problems with dims log-uniform
     in [lo, hi] (seed 100, not the benchmark's), operands uniform[-1, 1]
     on the device in the mode's element type."""
+    # the seeded input generators live beside the package, at the
+    # repository root
+    root = os.path.dirname(HERE)
+    if root not in sys.path:
+        sys.path.insert(0, root)
     import synth
     g = torch.Generator(device="cuda").manual_seed(100)
     ops = []
