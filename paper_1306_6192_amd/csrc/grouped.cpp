@@ -508,6 +508,7 @@ int gemm_tune_grouped_mix(const gemm_problem_t *ps, int32_t count, void *stream)
     std::vector<int> plan_of(nc, -1);
     std::vector<float> best_ms;
     void *image = nullptr;
+    size_t image_bytes = 0;
     for (int pass = 0; pass < 2 && rc == GEMM_OK; ++pass) {
         for (int c = 0; c < nc && rc == GEMM_OK; ++c) {
             t_variant_override = cands[c].variant;
@@ -532,10 +533,20 @@ int gemm_tune_grouped_mix(const gemm_problem_t *ps, int32_t count, void *stream)
             const size_t bytes = plan_image_bytes(plan);
             std::vector<uint8_t> host(bytes);
             plan_image_write(plan, host.data());
-            if (image) (void)hipFree(image);
-            image = nullptr;
-            if (hipMalloc(&image, bytes) != hipSuccess ||
-                hipMemcpy(image, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            // the previous candidate's launches have completed (time_median
+            // synchronises), so its image may be overwritten or replaced
+            if (bytes > image_bytes) {
+                if (image) (void)hipFree(image);
+                image = nullptr;
+                image_bytes = 0;
+                if (hipMalloc(&image, bytes) != hipSuccess) {
+                    (void)hipGetLastError();
+                    rc = fail(GEMM_EHIP, "grouped tuning descriptors");
+                    break;
+                }
+                image_bytes = bytes;
+            }
+            if (hipMemcpy(image, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
                 (void)hipGetLastError();
                 rc = fail(GEMM_EHIP, "grouped tuning descriptors");
                 break;
