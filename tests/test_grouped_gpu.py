@@ -190,3 +190,35 @@ def test_grouped_variant1_matches_plain_bitwise(mode, tmp_path):
                                "paper_1306_6192_amd", "tuning", "mi355x.jsonl")
         if os.path.exists(shipped):
             _lib.check(lib.gemm_tuner_load(shipped.encode()))
+
+
+def test_tune_grouped_mix_records_a_variant(tmp_path):
+    """gemm_tune_grouped_mix times the grouped kernel variants on a mixed
+    batch and records one for the mode (the launch results stay the plain
+    launch's bits whichever it picks); the shipped table is restored after."""
+    import os
+    log("grouped mix tuning")
+    lib = _lib.load()
+    mode = mg.MODE_BF16
+    probs, ops = _group(60, 32, 600, 21, mode)
+    arr = _lib.problems_array([mg.make_problem(a, b, c, mode) for a, b, c in ops])
+    stream = torch.cuda.current_stream().cuda_stream
+    try:
+        _lib.check(lib.gemm_tune_grouped_mix(arr, len(ops), stream))
+        info = (ctypes.c_int32 * 7)()
+        _lib.check(lib.gemm_grouped_info(mode, info))
+        assert info[6] in (0, 1)
+        f = tmp_path / "t.jsonl"
+        _lib.check(lib.gemm_tuner_save(str(f).encode()))
+        assert any(ln.startswith('{"grouped_eff": %d,' % mode) for ln in f.read_text().splitlines())
+        mg.grouped(ops, mode=mode)
+        for i, (a, b, c) in enumerate(ops):
+            assert np.array_equal(host(c), host(mg.gemm(a, b, mode=mode, cfg=3, split_k=1))), i
+    finally:
+        g = tmp_path / "r.jsonl"
+        g.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 0}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(g).encode()))
+        shipped = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                               "paper_1306_6192_amd", "tuning", "mi355x.jsonl")
+        if os.path.exists(shipped):
+            _lib.check(lib.gemm_tuner_load(shipped.encode()))
