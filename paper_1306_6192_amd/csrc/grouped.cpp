@@ -71,13 +71,21 @@ int grouped_choose_alone(int mode, int64_t m, int64_t n, int64_t k) {
     return grouped_model(mode, m, n, true, small_eff_of(mode));
 }
 
-// The mode's grouped kernel: the variant the autotuner measured fastest on a
-// mixed batch (gemm_tune_grouped_mix), else variant 0.
-const GroupedKernel *grouped_kernel(int mode) {
-    const int v = t_variant_override >= 0 ? t_variant_override : tuner_grouped_variant(mode);
-    if (mode == GEMM_MODE_F32) return f32_grouped(v);
-    return lp_grouped(mode, v);
+// Variant v (0 or 1) of the mode's grouped kernel (null for another v).
+static const GroupedKernel *grouped_variant(int mode, int v) {
+    if (v < 0 || v > 1) return nullptr;
+    return mode == GEMM_MODE_F32 ? f32_grouped(v) : lp_grouped(mode, v);
 }
+
+// The mode's grouped kernel: the variant the autotuner measured fastest on a
+// mixed batch (gemm_tune_grouped_mix), else (also for a variant this mode
+// does not have) variant 0.
+static int grouped_variant_of(int mode) {
+    const int v = t_variant_override >= 0 ? t_variant_override : tuner_grouped_variant(mode);
+    return grouped_variant(mode, v) ? v : 0;
+}
+
+const GroupedKernel *grouped_kernel(int mode) { return grouped_variant(mode, grouped_variant_of(mode)); }
 
 // Cost of one output tile in the static schedule, in microseconds of one
 // workgroup: its k-tiles, each bounded by the operand bytes it moves (16 KB
@@ -580,7 +588,7 @@ int gemm_grouped_info(int32_t mode, int32_t info[7]) {
     info[3] = gk->lds_bytes;
     info[4] = gk->alone_idx[0];
     info[5] = gk->alone_idx[1];
-    info[6] = t_variant_override >= 0 ? t_variant_override : tuner_grouped_variant(mode);
+    info[6] = grouped_variant_of(mode);
     return GEMM_OK;
 }
 
