@@ -250,6 +250,13 @@ def test_grouped_variant_from_the_table(mode, tmp_path):
         assert config_info(mode, cfg0)[:2] == [128, 128]
         _lib.check(lib.gemm_grouped_plan(arr, len(probs), out))
         assert set(out) == {cfg0}
+        # a variant the kernels do not have is not taken from a table: the
+        # line is skipped and the mode keeps the kernel it had
+        f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 1}\n' % mode)
+        _lib.check(lib.gemm_tuner_load(str(f).encode()))
+        f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 7}\n' % mode)
+        assert lib.gemm_tuner_load(str(f).encode()) == 0
+        assert grouped_info(mode)[6] == 1
     finally:
         f.write_text('{"grouped_eff": %d, "eff": 0.600, "variant": 0}\n' % mode)
         _lib.check(lib.gemm_tuner_load(str(f).encode()))
