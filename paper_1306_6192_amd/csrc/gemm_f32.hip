@@ -62,8 +62,8 @@ static const GroupedKernel kF32Grouped[2] = {
     make_grouped<F32Cfg<128, 128, 2, 2, 16>, F32Cfg<128, 128, 2, 2, 16>, GROUPED_ONE_OCC, GROUPED_ONE_DEPTH>(18, 18, 18,
                                                                                                          24),
     // (the 64 x 64 tile's accumulators share the 128 x 128 tile's first
-    // block, so the pair fits three workgroups per CU)
-    make_grouped<F32Cfg<128, 128, 2, 2, 16>, F32Cfg<64, 64, 2, 2, 32>, GROUPED_ONE_OCC, GROUPED_ONE_DEPTH>(18, 24, 18,
+    // block; the pair runs two workgroups per CU)
+    make_grouped<F32Cfg<128, 128, 2, 2, 16>, F32Cfg<64, 64, 2, 2, 32>, GROUPED_TWO_OCC, GROUPED_ONE_DEPTH>(18, 24, 18,
                                                                                                         24)};
 
 const GroupedKernel *f32_grouped(int variant) { return &kF32Grouped[variant]; }

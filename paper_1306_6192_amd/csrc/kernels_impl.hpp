@@ -26,8 +26,7 @@ template <int A, int B> struct cmax { static constexpr int v = A > B ? A : B; };
 // CU and depth of the register ring (k-tiles in flight: DEPTH - 1).
 //   0: one 128x128 tile, three workgroups per CU, one k-tile in flight;
 //   1: two tiles (128x128 and 64x64, the cost model choosing per problem),
-//      two workgroups per CU, three k-tiles in flight (FP32: three per CU,
-//      one in flight; its pair fits there).
+//      two workgroups per CU, three k-tiles in flight (FP32: one in flight).
 // On the 512-problem workload variant 0 measured faster: the stream is bound
 // by its per-step instructions, which more resident waves overlap, and the
 // second tile's registers or a deeper ring do not fit three workgroups.

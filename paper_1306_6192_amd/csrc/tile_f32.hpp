@@ -5,7 +5,8 @@
 // the k dimension in k-tiles of BK = 32 (or 16, half the LDS, for more
 // resident workgroups):
 //   HBM/L2 -> registers (16-B loads, masked at the edges)
-//          -> LDS (two stages, rows padded against bank conflicts)
+//          -> LDS (two stages; A chunks swizzled, B rows padded, against
+//             bank conflicts)
 //          -> MFMA fragments -> float32 accumulators in AGPRs/VGPRs.
 // The next k-tile's global loads are issued before the current k-tile's
 // MFMAs, and written to the other LDS stage after them: one barrier per
@@ -44,7 +45,11 @@ struct F32Cfg {
     static constexpr int THREADS = 64 * WM * WN;
     static constexpr int TM = BM / WM, TN = BN / WN;  // wave tile
     static constexpr int RB = TM / 32, CB = TN / 32;  // 32x32 blocks per wave
-    static constexpr int SA = BK + 4;                 // LDS row stride of A (floats)
+    // A rows are BK floats apart in LDS, their 16-byte chunks XOR-swizzled
+    // by row (a_swz): the staging writes (four or eight chunks of a row per
+    // lane group) and the fragment reads (one chunk of each of 16 rows per
+    // 16-lane phase) both hit 64 distinct banks
+    static constexpr int SA = BK;                     // LDS row stride of A (floats)
     static constexpr int SB = BN + 4;                 // LDS row stride of B (floats)
     static constexpr int A_ELEMS = BM * SA, B_ELEMS = BK * SB;
     static constexpr int STAGE = A_ELEMS + B_ELEMS;
@@ -57,6 +62,17 @@ struct F32Cfg {
                   "staging must cover the k-tile exactly");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
     static constexpr int MFMA_K = 2;
+    // physical chunk of logical chunk c in A row r: c ^ a_swz(r).  Four
+    // chunks per row (BK 16): 16 consecutive rows hold 4 of each (r mod 4)
+    // class, and bits 1-2 of r give those 4 distinct chunks (8 consecutive
+    // rows too: two of each (r mod 2) class).  Eight chunks (BK 32): 16 rows
+    // hold 8 of each (r mod 2) class, spread by bits 1-3.  The swizzle does
+    // not depend on the row's 32-row block, so a wave's fragment reads are
+    // constant offsets from one per-lane base per chunk.
+    __device__ static __forceinline__ int a_swz(int r) {
+        if constexpr (BK == 32) return (r >> 1) & 7;
+        return ((r >> 1) ^ (r >> 2)) & 3;
+    }
     __device__ static void run(const TileProblem &P, int tm, int tn, int split, uint8_t *lds);
 };
 
@@ -125,7 +141,7 @@ __device__ __forceinline__ void f32_store_tiles(float *stage, const f32x4 (&ra)[
         const int idx = tid + q * Cfg::THREADS;
         const int r = idx / (Cfg::BK / 4);
         const int kv = (idx % (Cfg::BK / 4)) * 4;
-        *reinterpret_cast<f32x4 *>(&As[r * Cfg::SA + kv]) = ra[q];
+        *reinterpret_cast<f32x4 *>(&As[r * Cfg::SA + 4 * ((kv / 4) ^ Cfg::a_swz(r))]) = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < Cfg::BV; ++q) {
@@ -143,7 +159,8 @@ __device__ __forceinline__ void f32_compute_stage(const float *stage, f32x16 (&a
     const int wave = threadIdx.x >> 6;
     const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
     const int l32 = lane & 31, g = lane >> 5;
-    const float *As = stage + (wm * Cfg::TM + l32) * Cfg::SA + 4 * g;
+    const int ar = wm * Cfg::TM + l32;                // row of row block 0
+    const float *As = stage + ar * Cfg::SA;
     const float *Bs = stage + Cfg::A_ELEMS + (4 * g) * Cfg::SB + wn * Cfg::TN + Cfg::CB * l32;
 #pragma unroll
     for (int kc = 0; kc < Cfg::BK / 8; ++kc) {
@@ -151,7 +168,7 @@ __device__ __forceinline__ void f32_compute_stage(const float *stage, f32x16 (&a
         BVec bf[4];
 #pragma unroll
         for (int rb = 0; rb < Cfg::RB; ++rb)
-            af[rb] = *reinterpret_cast<const f32x4 *>(As + rb * 32 * Cfg::SA + kc * 8);
+            af[rb] = *reinterpret_cast<const f32x4 *>(As + rb * 32 * Cfg::SA + 4 * ((2 * kc + g) ^ Cfg::a_swz(ar)));
 #pragma unroll
         for (int t = 0; t < 4; ++t)
             bf[t] = *reinterpret_cast<const BVec *>(Bs + (kc * 8 + t) * Cfg::SB);
