@@ -57,7 +57,18 @@ struct LpCfg {
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int RB = TM / 32, CB = TN / 32;
     static constexpr int RS = ROW + 16;          // padded LDS row stride in bytes (odd multiple of 16)
-    static constexpr int PLANE_A = BM * RS, PLANE_B = BN * RS;
+    // BF16 / F16: A rows unpadded, their 16-byte chunks XOR-swizzled by row
+    // (a_swz), so that the staging writes (several chunks of a few rows per
+    // 16-lane phase) and the fragment reads (one chunk of each of 16 rows)
+    // both hit 64 distinct banks; the padded stride puts the rows of one
+    // staging phase on overlapping banks.  FP8 and split-BF16x3 keep RS.
+    static constexpr bool SWZ_A = T::IN_ESZ == 2 && T::PLANES == 1;
+    static constexpr int RSA = SWZ_A ? ROW : RS;  // LDS row stride of A in bytes
+    __device__ static __forceinline__ int a_swz(int r) {
+        if constexpr (ROW / 16 == 8) return (r >> 1) & 7;
+        return ((r >> 1) ^ (r >> 2)) & 3;
+    }
+    static constexpr int PLANE_A = BM * RSA, PLANE_B = BN * RS;
     static constexpr int A_BYTES = T::PLANES * PLANE_A, B_BYTES = T::PLANES * PLANE_B;
     static constexpr int STAGE = A_BYTES + B_BYTES;
     static constexpr int LDS_BYTES = 2 * STAGE;
@@ -175,10 +186,12 @@ __device__ __forceinline__ void lp_store_tiles(uint8_t *stage, const LpStage<Cfg
             for (int e = 0; e < 4; ++e) split_bf16(__uint_as_float(R.a[q][e]), h[e], l[e]);
             const u32x2 hv = {h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
             const u32x2 lv = {l[0] | (l[1] << 16), l[2] | (l[3] << 16)};
-            *reinterpret_cast<u32x2 *>(As + r * Cfg::RS + v * 8) = hv;
-            *reinterpret_cast<u32x2 *>(As + Cfg::PLANE_A + r * Cfg::RS + v * 8) = lv;
+            *reinterpret_cast<u32x2 *>(As + r * Cfg::RSA + v * 8) = hv;
+            *reinterpret_cast<u32x2 *>(As + Cfg::PLANE_A + r * Cfg::RSA + v * 8) = lv;
+        } else if constexpr (Cfg::SWZ_A) {
+            *reinterpret_cast<u32x4 *>(As + r * Cfg::RSA + 16 * (v ^ Cfg::a_swz(r))) = R.a[q];
         } else {
-            *reinterpret_cast<u32x4 *>(As + r * Cfg::RS + v * 16) = R.a[q];
+            *reinterpret_cast<u32x4 *>(As + r * Cfg::RSA + v * 16) = R.a[q];
         }
     }
     // ---- B: transpose the thread's TKB x VN block into VN B^T rows
@@ -222,7 +235,8 @@ __device__ __forceinline__ void lp_compute_stage(const uint8_t *stage, f32x16 (&
     const int wave = threadIdx.x >> 6;
     const int wm = wave / Cfg::WN, wn = wave % Cfg::WN;
     const int l32 = lane & 31, g = lane >> 5;
-    const uint8_t *As = stage + (wm * Cfg::TM + l32) * Cfg::RS + g * Cfg::T::VB;
+    const int ar = wm * Cfg::TM + l32;             // A row of row block 0
+    const uint8_t *As = stage + ar * Cfg::RSA + (Cfg::SWZ_A ? 0 : g * Cfg::T::VB);
     const uint8_t *Bs = stage + Cfg::A_BYTES + (wn * Cfg::TN + l32) * Cfg::RS + g * Cfg::T::VB;
     constexpr int CHUNK_BYTES = 2 * Cfg::T::VB;   // bytes of one MFMA k-step in a row
 #pragma unroll
@@ -231,7 +245,7 @@ __device__ __forceinline__ void lp_compute_stage(const uint8_t *stage, f32x16 (&
             i32x8 af[Cfg::RB], bf[Cfg::CB];
 #pragma unroll
             for (int rb = 0; rb < Cfg::RB; ++rb) {
-                const uint8_t *p = As + rb * 32 * Cfg::RS + kc * CHUNK_BYTES;
+                const uint8_t *p = As + rb * 32 * Cfg::RSA + kc * CHUNK_BYTES;
                 const u32x4 lo = *reinterpret_cast<const u32x4 *>(p);
                 const u32x4 hi = *reinterpret_cast<const u32x4 *>(p + 16);
                 af[rb] = (i32x8){(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
@@ -255,7 +269,9 @@ __device__ __forceinline__ void lp_compute_stage(const uint8_t *stage, f32x16 (&
             u32x4 af[Cfg::RB], bf[Cfg::CB];
 #pragma unroll
             for (int rb = 0; rb < Cfg::RB; ++rb)
-                af[rb] = *reinterpret_cast<const u32x4 *>(As + rb * 32 * Cfg::RS + kc * CHUNK_BYTES);
+                af[rb] = *reinterpret_cast<const u32x4 *>(
+                    As + rb * 32 * Cfg::RSA +
+                    (Cfg::SWZ_A ? 16 * ((2 * kc + g) ^ Cfg::a_swz(ar)) : kc * CHUNK_BYTES));
 #pragma unroll
             for (int cb = 0; cb < Cfg::CB; ++cb)
                 bf[cb] = *reinterpret_cast<const u32x4 *>(Bs + cb * 32 * Cfg::RS + kc * CHUNK_BYTES);
@@ -263,7 +279,7 @@ __device__ __forceinline__ void lp_compute_stage(const uint8_t *stage, f32x16 (&
                 u32x4 al[Cfg::RB], bl[Cfg::CB];
 #pragma unroll
                 for (int rb = 0; rb < Cfg::RB; ++rb)
-                    al[rb] = *reinterpret_cast<const u32x4 *>(As + Cfg::PLANE_A + rb * 32 * Cfg::RS +
+                    al[rb] = *reinterpret_cast<const u32x4 *>(As + Cfg::PLANE_A + rb * 32 * Cfg::RSA +
                                                               kc * CHUNK_BYTES);
 #pragma unroll
                 for (int cb = 0; cb < Cfg::CB; ++cb)
