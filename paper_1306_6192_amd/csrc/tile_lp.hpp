@@ -57,12 +57,13 @@ struct LpCfg {
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int RB = TM / 32, CB = TN / 32;
     static constexpr int RS = ROW + 16;          // padded LDS row stride in bytes (odd multiple of 16)
-    // BF16 / F16: A rows unpadded, their 16-byte chunks XOR-swizzled by row
-    // (a_swz), so that the staging writes (several chunks of a few rows per
-    // 16-lane phase) and the fragment reads (one chunk of each of 16 rows)
-    // both hit 64 distinct banks; the padded stride puts the rows of one
-    // staging phase on overlapping banks.  FP8 and split-BF16x3 keep RS.
-    static constexpr bool SWZ_A = T::IN_ESZ == 2 && T::PLANES == 1;
+    // BF16 / F16 / FP8: A rows unpadded, their 16-byte chunks XOR-swizzled
+    // by row (a_swz), so that the staging writes (several chunks of a few
+    // rows per 16-lane phase) and the fragment reads (one chunk of each of
+    // 16 rows per read) both hit 64 distinct banks; the padded stride puts
+    // the rows of one staging phase on overlapping banks.  Split-BF16x3
+    // (two planes of 8-byte pieces) keeps RS.
+    static constexpr bool SWZ_A = T::PLANES == 1;
     static constexpr int RSA = SWZ_A ? ROW : RS;  // LDS row stride of A in bytes
     __device__ static __forceinline__ int a_swz(int r) {
         if constexpr (ROW / 16 == 8) return (r >> 1) & 7;
@@ -245,9 +246,13 @@ __device__ __forceinline__ void lp_compute_stage(const uint8_t *stage, f32x16 (&
             i32x8 af[Cfg::RB], bf[Cfg::CB];
 #pragma unroll
             for (int rb = 0; rb < Cfg::RB; ++rb) {
-                const uint8_t *p = As + rb * 32 * Cfg::RSA + kc * CHUNK_BYTES;
-                const u32x4 lo = *reinterpret_cast<const u32x4 *>(p);
-                const u32x4 hi = *reinterpret_cast<const u32x4 *>(p + 16);
+                // the lane's two chunks: 4 kc + 2 g and the next
+                const uint8_t *p = As + rb * 32 * Cfg::RSA;
+                const int c0 = 4 * kc + 2 * g;
+                const u32x4 lo = *reinterpret_cast<const u32x4 *>(
+                    p + (Cfg::SWZ_A ? 16 * (c0 ^ Cfg::a_swz(ar)) : kc * CHUNK_BYTES));
+                const u32x4 hi = *reinterpret_cast<const u32x4 *>(
+                    p + (Cfg::SWZ_A ? 16 * ((c0 + 1) ^ Cfg::a_swz(ar)) : kc * CHUNK_BYTES + 16));
                 af[rb] = (i32x8){(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
                                  (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
             }
